@@ -449,7 +449,8 @@ static cplx z2_entry(uint64_t seed, int64_t V, int64_t noise, int64_t site, int 
     uint64_t c = (uint64_t)(((noise * V + site) * 4 + spin) * 3 + col);
     uint64_t r = or_splitmix64(seed, c);
     double re = (r & 1) ? -1.0 : 1.0, im = (r & 2) ? -1.0 : 1.0;
-    return (re + _Complex_I * im) / sqrt(2.0);
+    /* sqrt(0.5) is the correctly rounded 1/sqrt(2) (one rounding, not two) */
+    return (re + _Complex_I * im) * sqrt(0.5);
 }
 
 /*
