@@ -1,0 +1,217 @@
+/*
+ * dloops.h -- C ABI of the MI355X (gfx950) library for disconnected quark
+ * loops with N_f = 2 Wilson fermions, after Alexandrou, Christaras, O Cais and
+ * Strelchenko, "Exact calculation of disconnected loops" (Lattice 2010).
+ *
+ * The method (Sections 2 and 3 of the paper): repeated Krylov inversions of
+ * the Wilson-Dirac matrix M = 1 - kappa D_hop on diluted complex-Z2 noise
+ * sources (or unit point sources, the exact method), followed by the local
+ * zero-momentum loop traces
+ *     L_Gamma(t) = sum_{x: x_4 = t} Tr[Gamma M^-1(x, x)],
+ * estimated per noise vector as sum_d eta_d^+ P_t Gamma M^-1 eta_d, and the
+ * truncated solver method's low/high-precision split.
+ *
+ * Conventions (the paper names Wilson fermions and a basis without writing
+ * them down; these are the readings used):
+ *   - dims = {X, Y, Z, T}, every extent even and >= 2; site index
+ *     i = x + X*(y + Y*(z + Z*t));
+ *   - canonical spinor field: complex128 [V][4 spin][3 colour], interleaved
+ *     (re, im) doubles; n fields are contiguous, [n][V][4][3];
+ *   - canonical gauge field: complex128 [4 mu][V][3][3], U_mu(x)_{ab};
+ *   - chiral basis gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_4 =
+ *     [[0, 1], [1, 0]], gamma_5 = gamma_1 gamma_2 gamma_3 gamma_4 =
+ *     diag(1, 1, -1, -1); Gamma_n = g1^n0 g2^n1 g3^n2 g4^n3 for
+ *     n = n0 + 2 n1 + 4 n2 + 8 n3 (Gamma_0 = 1, Gamma_15 = gamma_5,
+ *     Gamma_5 = gamma_1 gamma_3);
+ *   - (D psi)(x) = sum_mu (1 - gamma_mu) b U_mu(x) psi(x + mu)
+ *                      + (1 + gamma_mu) b U_mu(x - mu)^+ psi(x - mu),
+ *     Wilson r = 1, b = -1 on hops across the time boundary when it is
+ *     antiperiodic, +1 otherwise;
+ *   - complex Z2 noise: entry (noise n, site i, spin s, colour c) is output
+ *     number ((n*V + i)*4 + s)*3 + c of the SplitMix64 stream (Steele, Lea and
+ *     Flood 2014) seeded with `seed`; bit 0 gives the sign of the real part and
+ *     bit 1 that of the imaginary part (0 -> +), amplitude 1/sqrt(2);
+ *   - dilution (Section 2) scheme bits: 1 = spin-colour (12 classes,
+ *     d = 3 s + c), 2 = cubic spatial (8 classes, (x&1) + 2(y&1) + 4(z&1)),
+ *     4 = spatial even-odd (2 classes, (x+y+z+t)&1); enabled factors combine
+ *     in that order, the later factor running fastest.
+ *
+ * Every call returns a dl_status.  On failure dl_last_error() describes it
+ * (thread-local text, valid until the next call on the same thread).
+ * Arguments are validated before any device work; an invalid argument leaves
+ * every output untouched.  No C++ exception crosses this interface.
+ *
+ * Pointers are borrowed.  "device" pointers are HIP device memory on the
+ * current device (e.g. torch tensors' data_ptr()); "host" pointers are host
+ * memory.  `stream` is a hipStream_t (NULL = the default stream); device work
+ * is ordered on it and the call returns after the results it documents as
+ * host outputs are written.  Handles are owned by the caller, who destroys
+ * them; a handle is not used from two threads at once.
+ */
+#ifndef DLOOPS_H
+#define DLOOPS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DL_OK = 0,
+    DL_EINVAL = -1,        /* invalid argument (nothing was done) */
+    DL_ENOMEM = -2,        /* device allocation failed */
+    DL_EHIP = -3,          /* a HIP runtime call failed */
+    DL_ENOCONV = -4,       /* a solve did not reach its tolerance; best iterates written */
+    DL_EBREAKDOWN = -5,    /* Krylov breakdown that a restart could not cure */
+    DL_ENAN = -6,          /* non-finite value met in a solve */
+    DL_EUNSUPPORTED = -7   /* valid but not supported combination */
+} dl_status;
+
+/* storage precision of fields and links; arithmetic is FP64 for DL_F64 and
+   FP32 for the others (FP16 spinors carry one FP32 scale per site) */
+typedef enum { DL_F64 = 0, DL_F32 = 1, DL_F16 = 2, DL_BF16 = 3 } dl_prec;
+
+/* operators for dl_apply */
+typedef enum {
+    DL_OP_DHOP = 0,     /* D (hopping term), full lattice */
+    DL_OP_M = 1,        /* M = 1 - kappa D */
+    DL_OP_MDAG = 2,     /* M^dagger = 1 - kappa D^dagger */
+    DL_OP_MHAT = 3,     /* even-site Schur complement 1 - kappa^2 D_eo D_oe (odd part of
+                           input ignored, odd part of output set to zero) */
+    DL_OP_MHATDAG = 4,  /* its adjoint */
+    DL_OP_DHOPDAG = 5   /* D^dagger */
+} dl_op;
+
+typedef enum { DL_BICGSTAB = 0, DL_CGNR = 1 } dl_solver;
+
+typedef enum { DL_SRC_Z2 = 0, DL_SRC_POINT = 1 } dl_source_kind;
+
+typedef enum { DL_DIL_SPIN_COLOUR = 1, DL_DIL_CUBIC = 2, DL_DIL_EVEN_ODD = 4 } dl_dilution_bits;
+
+typedef struct dl_lattice_s *dl_lattice;
+typedef struct dl_gauge_s *dl_gauge;
+
+/* Description of the last failure on this thread ("" if none). */
+const char *dl_last_error(void);
+
+/* Library version string. */
+const char *dl_version(void);
+
+/*
+ * Create a lattice description.  dims: host int32[4] = {X, Y, Z, T}, each even
+ * and >= 2, V = XYZT <= 2^31 - 1.  t_antiperiodic: 1 = antiperiodic time
+ * boundary (b = -1 on hops across it), 0 = periodic.  Space is periodic.
+ * Errors: DL_EINVAL for a null pointer, odd or non-positive extents.
+ */
+int dl_lattice_create(const int32_t dims[4], int32_t t_antiperiodic, dl_lattice *out);
+void dl_lattice_destroy(dl_lattice lat);
+
+/* Lattice volume V (0 for a null handle). */
+int64_t dl_lattice_volume(dl_lattice lat);
+
+/*
+ * Upload a gauge field.  links: host canonical complex128 [4][V][3][3] of
+ * special-unitary matrices (the third row is rebuilt from the first two when
+ * recon = 12).  prec_mask: bit (1 << p) for each dl_prec p to keep resident
+ * on the device.  recon: 12 (store two rows, rebuild the third as the
+ * conjugated cross product) or 18 (store all three).  The time-boundary sign
+ * is never folded into the stored links.  The handle keeps its own reference
+ * to the lattice description; the lattice handle may be destroyed after.
+ * Errors: DL_EINVAL (null pointers, empty mask, recon not 12 or 18),
+ * DL_ENOMEM, DL_EHIP.
+ */
+int dl_gauge_create(dl_lattice lat, const double *links, uint32_t prec_mask, int32_t recon, void *stream,
+                    dl_gauge *out);
+void dl_gauge_destroy(dl_gauge g);
+
+/*
+ * out = op(in) for nrhs fields.  in, out: device canonical complex128
+ * [nrhs][V][4][3]; they must not overlap.  prec: storage precision of the
+ * links and fields the operator runs in (must be resident in the gauge
+ * handle); results are converted back to complex128.  kappa is ignored for
+ * DL_OP_DHOP / DL_OP_DHOPDAG.  Errors: DL_EINVAL (null pointer, nrhs < 1,
+ * unknown op, precision not resident), DL_ENOMEM, DL_EHIP.
+ */
+int dl_apply(dl_gauge g, double kappa, int32_t op, int32_t prec, const void *in, void *out, int64_t nrhs,
+             void *stream);
+
+/* Solver parameters. */
+typedef struct {
+    int32_t solver;      /* DL_BICGSTAB or DL_CGNR (CG on the normal equations of the Schur system) */
+    int32_t prec;        /* storage precision of the iterated vectors; below DL_F64 a tolerance-driven
+                            BiCGStab runs with FP64 reliable updates of x and of the residual */
+    double tol;          /* stop when the FP64 true residual |b - M x| / |b| <= tol (fixed_iters = 0) */
+    int32_t maxiter;     /* iteration cap (tolerance-driven solves) */
+    int32_t fixed_iters; /* > 0: run exactly this many iterations from x0 = 0 (truncated solve) */
+    double delta;        /* reliable-update trigger: |r| < delta * max |r| since the last update
+                            (0 -> 0.1) */
+    int32_t poll;        /* iterations between host convergence checks (0 -> automatic) */
+} dl_solve_params;
+
+/* Per right-hand side results of a solve. */
+typedef struct {
+    int32_t status;           /* DL_OK, DL_ENOCONV, DL_ENAN */
+    int32_t iters;            /* Krylov iterations */
+    int32_t reliable_updates; /* FP64 residual replacements */
+    int32_t pad;
+    double true_rel_residual; /* FP64 |b - M x| / |b| of the returned solution */
+} dl_solve_stats;
+
+/*
+ * Solve M x = b (even-odd preconditioned: the Schur system on even sites,
+ * then x_o = b_o + kappa D_oe x_e) for nrhs right-hand sides.  b, x: device
+ * canonical complex128 [nrhs][V][4][3], not overlapping.  stats: host
+ * [nrhs] or NULL.  Returns DL_ENOCONV if any tolerance-driven solve did not
+ * converge within maxiter (x holds the last iterate).
+ */
+int dl_solve(dl_gauge g, double kappa, const dl_solve_params *params, const void *b, void *x, int64_t nrhs,
+             dl_solve_stats *stats, void *stream);
+
+/* Sources of a loop estimate. */
+typedef struct {
+    int32_t kind;        /* DL_SRC_Z2: complex Z2 noise; DL_SRC_POINT: the 12 unit sources at one site */
+    int32_t scheme;      /* DL_SRC_Z2: dilution bits (0 = undiluted) */
+    uint64_t seed;       /* DL_SRC_Z2: SplitMix64 seed */
+    int64_t first_noise; /* DL_SRC_Z2: noise numbers first_noise .. first_noise + n_noise - 1 */
+    int32_t n_noise;     /* DL_SRC_Z2: number of noise vectors; DL_SRC_POINT: must be 1 */
+    int32_t point_site;  /* DL_SRC_POINT: lexicographic site index */
+} dl_sources;
+
+/*
+ * Loop estimate (Sections 2-3): for every noise n and dilution class d solve
+ * M s = eta_{n,d} and accumulate
+ *     loops[n][g][t] = sum_d sum_{x: x_4 = t} eta_{n,d}(x)^+ Gamma_{gammas[g]} s(x),
+ * a per-noise sum over dilution classes (not a mean).  For DL_SRC_POINT the
+ * single "noise" is the set of 12 unit sources at point_site and
+ * loops[0][g][t(site)] = Tr[Gamma M^-1(site, site)] exactly.
+ * gammas: host int32[n_gamma], each in [0, 15], 1 <= n_gamma <= 16.
+ * loops: host double [n_noise][n_gamma][T][2].  stats: host [n_noise * classes]
+ * (right-hand side order: noise-major, then dilution class) or NULL.
+ */
+int dl_loops(dl_gauge g, double kappa, const dl_sources *src, const dl_solve_params *params,
+             const int32_t *gammas, int32_t n_gamma, double *loops, dl_solve_stats *stats, void *stream);
+
+/* Number of right-hand sides (solves) a dl_sources description expands to, or < 0 if invalid. */
+int64_t dl_sources_count(dl_lattice lat, const dl_sources *src);
+
+/*
+ * Write right-hand sides first_rhs .. first_rhs + nrhs - 1 of a dl_sources
+ * description (noise-major, then dilution class) into out: device canonical
+ * complex128 [nrhs][V][4][3].  These are exactly the vectors dl_loops solves
+ * for.  Errors: DL_EINVAL (invalid sources, range outside [0, count)).
+ */
+int dl_sources_fill(dl_lattice lat, const dl_sources *src, int64_t first_rhs, int64_t nrhs, void *out, void *stream);
+
+/* Time spent in the library's kernels since profiling was enabled.  kind:
+   0 = hopping (dslash) kernels, 1 = Krylov vector kernels, 2 = sources and
+   traces.  Returns launches; *ms = summed event-timed duration, *bytes = the
+   algorithmic bytes of those launches (each operand moved once). */
+int dl_profile_enable(int32_t on);
+int64_t dl_profile_read(int32_t kind, double *ms, double *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DLOOPS_H */

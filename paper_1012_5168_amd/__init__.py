@@ -1,0 +1,296 @@
+"""Python binding of ``libdloops.so``, the MI355X (gfx950) library for
+disconnected quark loops with N_f = 2 Wilson fermions.
+
+The binding only marshals arguments: every step of the computation runs in
+the library's HIP kernels.  Torch supplies device memory and the stream.
+Function names match the C ABI declared in ``include/dloops.h``; the classes
+:class:`Lattice` and :class:`Gauge` own the library handles, and
+:func:`apply`, :func:`solve` and :func:`loops` are tensor-level shorthands.
+
+The library is built in-tree by :func:`paper_1012_5168_amd._build.build`.
+Loading fails loudly when it is missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBRARY_PATH = os.path.join(_HERE, "libdloops.so")
+
+# ------------------------------------------------------------------ constants (dloops.h)
+DL_OK, DL_EINVAL, DL_ENOMEM, DL_EHIP, DL_ENOCONV, DL_EBREAKDOWN, DL_ENAN, DL_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+DL_F64, DL_F32, DL_F16, DL_BF16 = 0, 1, 2, 3
+DL_OP_DHOP, DL_OP_M, DL_OP_MDAG, DL_OP_MHAT, DL_OP_MHATDAG, DL_OP_DHOPDAG = 0, 1, 2, 3, 4, 5
+DL_BICGSTAB, DL_CGNR = 0, 1
+DL_SRC_Z2, DL_SRC_POINT = 0, 1
+DL_DIL_SPIN_COLOUR, DL_DIL_CUBIC, DL_DIL_EVEN_ODD = 1, 2, 4
+
+_STATUS = {
+    DL_EINVAL: "DL_EINVAL",
+    DL_ENOMEM: "DL_ENOMEM",
+    DL_EHIP: "DL_EHIP",
+    DL_ENOCONV: "DL_ENOCONV",
+    DL_EBREAKDOWN: "DL_EBREAKDOWN",
+    DL_ENAN: "DL_ENAN",
+    DL_EUNSUPPORTED: "DL_EUNSUPPORTED",
+}
+
+
+class DLError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (_STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class dl_solve_params(ctypes.Structure):
+    _fields_ = [
+        ("solver", ctypes.c_int32),
+        ("prec", ctypes.c_int32),
+        ("tol", ctypes.c_double),
+        ("maxiter", ctypes.c_int32),
+        ("fixed_iters", ctypes.c_int32),
+        ("delta", ctypes.c_double),
+        ("poll", ctypes.c_int32),
+    ]
+
+
+class dl_solve_stats(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("iters", ctypes.c_int32),
+        ("reliable_updates", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+        ("true_rel_residual", ctypes.c_double),
+    ]
+
+
+class dl_sources(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("scheme", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("first_noise", ctypes.c_int64),
+        ("n_noise", ctypes.c_int32),
+        ("point_site", ctypes.c_int32),
+    ]
+
+
+_P = ctypes.c_void_p
+_SIGNATURES = {
+    "dl_last_error": (ctypes.c_char_p, []),
+    "dl_version": (ctypes.c_char_p, []),
+    "dl_lattice_create": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(_P)]),
+    "dl_lattice_destroy": (None, [_P]),
+    "dl_lattice_volume": (ctypes.c_int64, [_P]),
+    "dl_gauge_create": (ctypes.c_int, [_P, _P, ctypes.c_uint32, ctypes.c_int32, _P, ctypes.POINTER(_P)]),
+    "dl_gauge_destroy": (None, [_P]),
+    "dl_apply": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int64, _P]),
+    "dl_solve": (ctypes.c_int, [_P, ctypes.c_double, ctypes.POINTER(dl_solve_params), _P, _P, ctypes.c_int64,
+                                ctypes.POINTER(dl_solve_stats), _P]),
+    "dl_loops": (ctypes.c_int, [_P, ctypes.c_double, ctypes.POINTER(dl_sources), ctypes.POINTER(dl_solve_params), _P,
+                                ctypes.c_int32, _P, ctypes.POINTER(dl_solve_stats), _P]),
+    "dl_sources_count": (ctypes.c_int64, [_P, ctypes.POINTER(dl_sources)]),
+    "dl_sources_fill": (ctypes.c_int, [_P, ctypes.POINTER(dl_sources), ctypes.c_int64, ctypes.c_int64, _P, _P]),
+    "dl_profile_enable": (ctypes.c_int, [ctypes.c_int32]),
+    "dl_profile_read": (ctypes.c_int64, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double)]),
+}
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load the in-tree library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIBRARY_PATH
+    if not os.path.exists(path):
+        raise RuntimeError("libdloops.so is not built (%s); run paper_1012_5168_amd._build.build()" % path)
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return list(_SIGNATURES)
+
+
+def _check(rc: int, allow=()):
+    if rc != DL_OK and rc not in allow:
+        raise DLError(rc, load().dl_last_error().decode())
+    return rc
+
+
+def _stream(stream=None):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ same-name wrappers
+
+
+def dl_last_error() -> str:
+    return load().dl_last_error().decode()
+
+
+def dl_version() -> str:
+    return load().dl_version().decode()
+
+
+def dl_lattice_create(dims, t_antiperiodic: int = 1):
+    d = (ctypes.c_int32 * 4)(*[int(x) for x in dims])
+    h = _P()
+    _check(load().dl_lattice_create(d, int(t_antiperiodic), ctypes.byref(h)))
+    return h
+
+
+def dl_lattice_destroy(h):
+    load().dl_lattice_destroy(h)
+
+
+def dl_gauge_create(lat, links: np.ndarray, prec_mask: int, recon: int = 12, stream=None):
+    links = np.ascontiguousarray(links, dtype=np.complex128)
+    h = _P()
+    _check(load().dl_gauge_create(lat, links.ctypes.data_as(_P), int(prec_mask), int(recon), _stream(stream),
+                                  ctypes.byref(h)))
+    return h
+
+
+def dl_gauge_destroy(h):
+    load().dl_gauge_destroy(h)
+
+
+def dl_apply(gauge, kappa, op, prec, inp, out, nrhs, stream=None):
+    _check(load().dl_apply(gauge, float(kappa), int(op), int(prec), _dptr(inp), _dptr(out), int(nrhs),
+                           _stream(stream)))
+
+
+def dl_solve(gauge, kappa, params, b, x, nrhs, stats=None, stream=None):
+    st = (dl_solve_stats * int(nrhs))() if stats is None else stats
+    rc = load().dl_solve(gauge, float(kappa), ctypes.byref(params), _dptr(b), _dptr(x), int(nrhs), st,
+                         _stream(stream))
+    _check(rc, allow=(DL_ENOCONV,))
+    return rc, st
+
+
+def dl_loops(gauge, kappa, sources, params, gammas, loops_out: np.ndarray, stats=None, stream=None):
+    g = np.ascontiguousarray(np.asarray(gammas, dtype=np.int32))
+    rc = load().dl_loops(gauge, float(kappa), ctypes.byref(sources), ctypes.byref(params), g.ctypes.data_as(_P),
+                         len(g), loops_out.ctypes.data_as(_P), stats, _stream(stream))
+    _check(rc, allow=(DL_ENOCONV,))
+    return rc
+
+
+def dl_sources_count(lat, sources) -> int:
+    n = load().dl_sources_count(lat, ctypes.byref(sources))
+    if n < 0:
+        _check(int(n))
+    return int(n)
+
+
+def dl_sources_fill(lat, sources, first_rhs, nrhs, out, stream=None):
+    _check(load().dl_sources_fill(lat, ctypes.byref(sources), int(first_rhs), int(nrhs), _dptr(out), _stream(stream)))
+
+
+def dl_profile_enable(on: bool = True):
+    load().dl_profile_enable(1 if on else 0)
+
+
+def dl_profile_read(kind: int):
+    ms, by = ctypes.c_double(), ctypes.c_double()
+    n = load().dl_profile_read(int(kind), ctypes.byref(ms), ctypes.byref(by))
+    return int(n), ms.value, by.value
+
+
+# ------------------------------------------------------------------ handles and shorthands
+
+
+def solve_params(solver=DL_BICGSTAB, prec=DL_F64, tol=1e-10, maxiter=1000, fixed_iters=0, delta=0.0, poll=0):
+    return dl_solve_params(int(solver), int(prec), float(tol), int(maxiter), int(fixed_iters), float(delta), int(poll))
+
+
+def z2_sources(seed, n_noise, first_noise=0, scheme=0):
+    return dl_sources(DL_SRC_Z2, int(scheme), int(seed) & (2**64 - 1), int(first_noise), int(n_noise), 0)
+
+
+def point_sources(site):
+    return dl_sources(DL_SRC_POINT, 0, 0, 0, 1, int(site))
+
+
+class Lattice:
+    def __init__(self, dims, t_antiperiodic=True):
+        self.dims = tuple(int(d) for d in dims)
+        self.V = int(np.prod(self.dims))
+        self.h = dl_lattice_create(self.dims, 1 if t_antiperiodic else 0)
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            dl_lattice_destroy(self.h)
+            self.h = None
+
+
+class Gauge:
+    def __init__(self, lattice: Lattice, links: np.ndarray, precs=(DL_F64,), recon=12, stream=None):
+        self.lattice = lattice
+        mask = 0
+        for p in precs:
+            mask |= 1 << int(p)
+        self.h = dl_gauge_create(lattice.h, links, mask, recon, stream)
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            dl_gauge_destroy(self.h)
+            self.h = None
+
+
+def apply(gauge: Gauge, kappa: float, op: int, psi, prec=DL_F64):
+    """op(psi) for a device complex128 tensor psi of shape [n][V][4][3] (or [V][4][3])."""
+    import torch
+
+    x = psi.contiguous()
+    if x.dim() == 3:
+        x = x.unsqueeze(0)
+    out = torch.empty_like(x)
+    dl_apply(gauge.h, kappa, op, prec, x, out, x.shape[0])
+    return out.reshape(psi.shape)
+
+
+def solve(gauge: Gauge, kappa: float, b, params=None):
+    """Solve M x = b for a device complex128 tensor b [n][V][4][3]; returns (x, stats list)."""
+    import torch
+
+    params = params or solve_params()
+    bb = b.contiguous()
+    if bb.dim() == 3:
+        bb = bb.unsqueeze(0)
+    x = torch.empty_like(bb)
+    _, st = dl_solve(gauge.h, kappa, params, bb, x, bb.shape[0])
+    return x.reshape(b.shape), [(s.status, s.iters, s.reliable_updates, s.true_rel_residual) for s in st]
+
+
+def loops(gauge: Gauge, kappa: float, sources: dl_sources, gammas, params=None, stream=None):
+    """Per-noise loop estimates, complex [n_noise][n_gamma][T], and per-solve stats."""
+    params = params or solve_params()
+    T = gauge.lattice.dims[3]
+    n = int(sources.n_noise)
+    buf = np.zeros((n, len(gammas), T, 2), dtype=np.float64)
+    nrhs = dl_sources_count(gauge.lattice.h, sources)
+    st = (dl_solve_stats * nrhs)()
+    dl_loops(gauge.h, kappa, sources, params, gammas, buf, st, stream)
+    stats = [(s.status, s.iters, s.reliable_updates, s.true_rel_residual) for s in st]
+    return buf[..., 0] + 1j * buf[..., 1], stats

@@ -1,0 +1,261 @@
+// dl_common.hpp -- device-side building blocks shared by the HIP kernels:
+// complex arithmetic, storage formats of spinor and link fields, even-odd
+// site geometry, wavefront reductions and the XCD-aware block order.
+//
+// Device layouts (private to the library):
+//   half-spinor field of one parity, one right-hand side: 12 complex
+//   components (spin-major, then colour) stored structure-of-arrays,
+//   component e of checkerboard site cb at [e * Vh + cb]; nrhs fields follow
+//   each other with stride 12 * Vh.  FP16 fields carry an extra FP32 scale
+//   per site ([rhs * Vh + cb]) and store entries divided by it.
+//   links: [mu][parity][NE][Vh] complex with NE = 6 (rows 0-1, the third row
+//   is rebuilt as the conjugated cross product) or 9.  U_mu(x) of a site x of
+//   parity p sits at [mu][p][.][cb(x)].
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dl {
+
+// ---------------------------------------------------------------- complex
+
+template <typename R>
+struct cx {
+    R re, im;
+};
+
+template <typename R>
+__device__ __forceinline__ cx<R> mk(R a, R b) { return cx<R>{a, b}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a) { return {-a.re, -a.im}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> operator*(R s, cx<R> a) { return {s * a.re, s * a.im}; }
+template <typename R>
+__device__ __forceinline__ cx<R> conj(cx<R> a) { return {a.re, -a.im}; }
+// i * a
+template <typename R>
+__device__ __forceinline__ cx<R> times_i(cx<R> a) { return {-a.im, a.re}; }
+// acc += a * b
+template <typename R>
+__device__ __forceinline__ void cmac(cx<R> &acc, cx<R> a, cx<R> b)
+{
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(-a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(a.im, b.re, acc.im);
+}
+// acc += conj(a) * b
+template <typename R>
+__device__ __forceinline__ void cmac_conj(cx<R> &acc, cx<R> a, cx<R> b)
+{
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(-a.im, b.re, acc.im);
+}
+
+// ---------------------------------------------------------------- storage formats
+
+// Storage type S -> arithmetic type R and the packed complex element.
+template <typename S>
+struct Fmt;
+template <>
+struct Fmt<double> {
+    using R = double;
+    using E = double2;
+    static constexpr bool scaled = false;
+    __device__ static __forceinline__ cx<double> ld(const E *p, int64_t i)
+    {
+        E v = p[i];
+        return {v.x, v.y};
+    }
+    __device__ static __forceinline__ void st(E *p, int64_t i, cx<double> v) { p[i] = make_double2(v.re, v.im); }
+};
+template <>
+struct Fmt<float> {
+    using R = float;
+    using E = float2;
+    static constexpr bool scaled = false;
+    __device__ static __forceinline__ cx<float> ld(const E *p, int64_t i)
+    {
+        E v = p[i];
+        return {v.x, v.y};
+    }
+    __device__ static __forceinline__ void st(E *p, int64_t i, cx<float> v) { p[i] = make_float2(v.re, v.im); }
+};
+template <>
+struct Fmt<__half> {
+    using R = float;
+    using E = __half2;
+    static constexpr bool scaled = true;
+    __device__ static __forceinline__ cx<float> ld(const E *p, int64_t i)
+    {
+        float2 v = __half22float2(p[i]);
+        return {v.x, v.y};
+    }
+    __device__ static __forceinline__ void st(E *p, int64_t i, cx<float> v)
+    {
+        p[i] = __float22half2_rn(make_float2(v.re, v.im));
+    }
+};
+template <>
+struct Fmt<__hip_bfloat16> {
+    using R = float;
+    using E = __hip_bfloat162;
+    static constexpr bool scaled = false;
+    __device__ static __forceinline__ cx<float> ld(const E *p, int64_t i)
+    {
+        float2 v = __bfloat1622float2(p[i]);
+        return {v.x, v.y};
+    }
+    __device__ static __forceinline__ void st(E *p, int64_t i, cx<float> v)
+    {
+        p[i] = __float22bfloat162_rn(make_float2(v.re, v.im));
+    }
+};
+
+// A set of nrhs half-spinor fields of one parity.
+struct Field {
+    void *d;       // [nrhs][12][Vh] packed complex of the storage type
+    float *nrm;    // [nrhs][Vh] per-site scale (FP16 only, else null)
+};
+
+template <typename S>
+__device__ __forceinline__ void load_spinor(const Field &f, int64_t Vh, int rhs, int64_t cb,
+                                            cx<typename Fmt<S>::R> v[12])
+{
+    using F = Fmt<S>;
+    using R = typename F::R;
+    const typename F::E *p = static_cast<const typename F::E *>(f.d) + (int64_t)rhs * 12 * Vh + cb;
+#pragma unroll
+    for (int e = 0; e < 12; ++e) v[e] = F::ld(p, e * Vh);
+    if constexpr (F::scaled) {
+        R s = f.nrm[(int64_t)rhs * Vh + cb];
+#pragma unroll
+        for (int e = 0; e < 12; ++e) v[e] = s * v[e];
+    }
+}
+
+template <typename S>
+__device__ __forceinline__ void store_spinor(const Field &f, int64_t Vh, int rhs, int64_t cb,
+                                             const cx<typename Fmt<S>::R> v[12])
+{
+    using F = Fmt<S>;
+    using R = typename F::R;
+    typename F::E *p = static_cast<typename F::E *>(f.d) + (int64_t)rhs * 12 * Vh + cb;
+    if constexpr (F::scaled) {
+        R m = 0;
+#pragma unroll
+        for (int e = 0; e < 12; ++e) m = fmaxf(m, fmaxf(fabsf(v[e].re), fabsf(v[e].im)));
+        f.nrm[(int64_t)rhs * Vh + cb] = m;
+        R inv = m > 0 ? R(1) / m : R(0);
+#pragma unroll
+        for (int e = 0; e < 12; ++e) F::st(p, e * Vh, inv * v[e]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 12; ++e) F::st(p, e * Vh, v[e]);
+    }
+}
+
+// Link field of one precision: [4][2][NE][Vh].
+template <typename S, int NE>
+__device__ __forceinline__ void load_link(const void *links, int64_t Vh, int mu, int par, int64_t cb,
+                                          cx<typename Fmt<S>::R> u[9])
+{
+    using F = Fmt<S>;
+    const typename F::E *p = static_cast<const typename F::E *>(links) + ((int64_t)(mu * 2 + par) * NE) * Vh + cb;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) u[e] = F::ld(p, e * Vh);
+    if constexpr (NE == 6) {
+        // third row = conj(row0 x row1) of a special-unitary matrix
+        u[6] = conj(u[1] * u[5] - u[2] * u[4]);
+        u[7] = conj(u[2] * u[3] - u[0] * u[5]);
+        u[8] = conj(u[0] * u[4] - u[1] * u[3]);
+    }
+}
+
+// ---------------------------------------------------------------- geometry
+
+struct Geom {
+    int X, Y, Z, T;  // full extents
+    int Xh;          // X / 2
+    int Vh;          // sites per parity
+    int sY, sZ, sT;  // checkerboard strides of y, z, t: Xh, Xh*Y, Xh*Y*Z
+    int tap;         // antiperiodic time boundary
+};
+
+struct Site {
+    int x, y, z, t;
+};
+
+// coordinates of checkerboard site cb of parity p
+__device__ __forceinline__ Site decode(const Geom &g, int cb, int p)
+{
+    Site s;
+    int r = cb / g.Xh;
+    int k = cb - r * g.Xh;
+    int r2 = r / g.Y;
+    s.y = r - r2 * g.Y;
+    s.t = r2 / g.Z;
+    s.z = r2 - s.t * g.Z;
+    s.x = 2 * k + ((p + s.y + s.z + s.t) & 1);
+    return s;
+}
+
+// ---------------------------------------------------------------- reductions
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Deterministic block sum of N values per thread; result valid in thread 0.
+// scratch: __shared__ double[N * (blockDim/64)].
+template <int N>
+__device__ __forceinline__ void block_sum(double v[N], double *scratch)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < N; ++k) scratch[wid * N + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            double s = 0;
+            for (int w = 0; w < nw; ++w) s += scratch[w * N + k];
+            v[k] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- block order
+
+// The hardware hands consecutive workgroups to the 8 XCDs in turn.  Remap so
+// that each XCD works through a contiguous range of logical blocks: the
+// neighbour sites a block gathers then sit in the same XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int nblocks)
+{
+    const int nx = 8;
+    int q = nblocks / nx, rem = nblocks % nx;
+    int xcd = b % nx, j = b / nx;
+    return xcd * q + min(xcd, rem) + j;
+}
+
+}  // namespace dl

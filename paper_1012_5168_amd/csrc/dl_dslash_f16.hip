@@ -1,0 +1,6 @@
+// dl_dslash_f16.hip -- hopping kernels with __half storage.
+#include "dl_dslash_inst.hpp"
+
+namespace dl {
+template void launch_dslash_t<__half>(const DslashCall &c, int nr, int bs, hipStream_t s);
+}  // namespace dl

@@ -1,0 +1,6 @@
+// dl_dslash_f32.hip -- hopping kernels with float storage.
+#include "dl_dslash_inst.hpp"
+
+namespace dl {
+template void launch_dslash_t<float>(const DslashCall &c, int nr, int bs, hipStream_t s);
+}  // namespace dl

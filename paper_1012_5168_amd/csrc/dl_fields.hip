@@ -1,0 +1,259 @@
+// dl_fields.hip -- layout conversion (canonical <-> even-odd SoA), noise and
+// point sources with dilution masks, the timeslice trace reduction and the
+// gamma contraction of the loops, and link-format conversion.
+#include "dl_internal.hpp"
+
+namespace dl {
+
+namespace {
+
+constexpr int BS = 256;
+
+__device__ __forceinline__ int64_t lex_index(const Geom &g, const Site &s)
+{
+    return s.x + (int64_t)g.X * (s.y + (int64_t)g.Y * (s.z + (int64_t)g.Z * s.t));
+}
+
+// ---------------------------------------------------------------- noise
+
+// SplitMix64 (Steele, Lea and Flood, 2014): the stream seeded with `seed`
+// adds the odd constant 0x9e3779b97f4a7c15 to its state before every output
+// and returns the state passed through a two-round xor-shift-multiply
+// finaliser.  Output number n (from 0) therefore only needs the state
+// seed + (n + 1) * constant, which makes every noise entry independent.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t n)
+{
+    uint64_t z = seed + (n + 1ull) * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// class of entry (site, spin, colour) under the dilution bits
+__device__ __forceinline__ int dil_class(int scheme, const Site &s, int spin, int col)
+{
+    int d = 0;
+    if (scheme & DL_DIL_SPIN_COLOUR) d = d * 12 + 3 * spin + col;
+    if (scheme & DL_DIL_CUBIC) d = d * 8 + (s.x & 1) + 2 * (s.y & 1) + 4 * (s.z & 1);
+    if (scheme & DL_DIL_EVEN_ODD) d = d * 2 + ((s.x + s.y + s.z + s.t) & 1);
+    return d;
+}
+
+// source entries of one site for one right-hand side
+__device__ __forceinline__ void source_site(const SourceSpec &src, int rhs, const Site &st, int64_t lex,
+                                            cx<double> eta[12])
+{
+    const int cls = src.cls[rhs];
+    if (src.kind == DL_SRC_POINT) {
+#pragma unroll
+        for (int e = 0; e < 12; ++e) eta[e] = {(lex == src.point_site && e == cls) ? 1.0 : 0.0, 0.0};
+        return;
+    }
+    const double amp = 0.70710678118654752440;  // 1/sqrt(2)
+    const uint64_t base = ((uint64_t)src.noise[rhs] * (uint64_t)src.V + (uint64_t)lex) * 12ull;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int e = 3 * sp + c;
+            if (src.scheme != 0 && dil_class(src.scheme, st, sp, c) != cls) {
+                eta[e] = {0.0, 0.0};
+                continue;
+            }
+            const uint64_t r = splitmix64_at(src.seed, base + (uint64_t)e);
+            eta[e] = {(r & 1ull) ? -amp : amp, (r & 2ull) ? -amp : amp};
+        }
+}
+
+// ---------------------------------------------------------------- kernels
+
+template <typename S>
+__global__ __launch_bounds__(BS) void pack_kernel(Field dst, int parity, const double *canon, Geom g)
+{
+    using R = typename Fmt<S>::R;
+    const int rhs = blockIdx.y;
+    const int cb = blockIdx.x * BS + threadIdx.x;
+    if (cb >= g.Vh) return;
+    const Site s = decode(g, cb, parity);
+    const int64_t V = 2 * (int64_t)g.Vh;
+    const double2 *src = reinterpret_cast<const double2 *>(canon) + ((int64_t)rhs * V + lex_index(g, s)) * 12;
+    cx<R> v[12];
+#pragma unroll
+    for (int e = 0; e < 12; ++e) {
+        double2 z = src[e];
+        v[e] = {R(z.x), R(z.y)};
+    }
+    store_spinor<S>(dst, g.Vh, rhs, cb, v);
+}
+
+template <typename S>
+__global__ __launch_bounds__(BS) void unpack_kernel(Field src, int parity, double *canon, Geom g)
+{
+    using R = typename Fmt<S>::R;
+    const int rhs = blockIdx.y;
+    const int cb = blockIdx.x * BS + threadIdx.x;
+    if (cb >= g.Vh) return;
+    const Site s = decode(g, cb, parity);
+    const int64_t V = 2 * (int64_t)g.Vh;
+    double2 *dst = reinterpret_cast<double2 *>(canon) + ((int64_t)rhs * V + lex_index(g, s)) * 12;
+    cx<R> v[12];
+    load_spinor<S>(src, g.Vh, rhs, cb, v);
+#pragma unroll
+    for (int e = 0; e < 12; ++e) dst[e] = make_double2((double)v[e].re, (double)v[e].im);
+}
+
+template <typename S>
+__global__ __launch_bounds__(BS) void source_kernel(Field dst, int parity, SourceSpec src, Geom g)
+{
+    using R = typename Fmt<S>::R;
+    const int rhs = blockIdx.y;
+    const int cb = blockIdx.x * BS + threadIdx.x;
+    if (cb >= g.Vh) return;
+    const Site s = decode(g, cb, parity);
+    cx<double> eta[12];
+    source_site(src, rhs, s, lex_index(g, s), eta);
+    cx<R> v[12];
+#pragma unroll
+    for (int e = 0; e < 12; ++e) v[e] = {R(eta[e].re), R(eta[e].im)};
+    store_spinor<S>(dst, g.Vh, rhs, cb, v);
+}
+
+// One block per (timeslice, right-hand side); threads stride over the
+// timeslice's sites of both parities and accumulate the 4x4 colour-traced
+// spin matrix C[a][b] = sum_c conj(eta_{a c}) s_{b c} in FP64.
+template <typename S>
+__global__ __launch_bounds__(BS) void trace_kernel(Field se, Field so, SourceSpec src, Geom g, double *C)
+{
+    using R = typename Fmt<S>::R;
+    __shared__ double red[32 * (BS / 64)];
+    const int t = blockIdx.x, rhs = blockIdx.y;
+    const int per = g.sT;  // checkerboard sites per timeslice and parity
+    double acc[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) acc[k] = 0;
+    for (int j = threadIdx.x; j < 2 * per; j += BS) {
+        const int par = j >= per ? 1 : 0;
+        const int cb = t * per + (j - par * per);
+        const Site s = decode(g, cb, par);
+        cx<double> eta[12];
+        source_site(src, rhs, s, lex_index(g, s), eta);
+        cx<R> sv[12];
+        load_spinor<S>(par ? so : se, g.Vh, rhs, cb, sv);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                double re = 0, im = 0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const cx<double> e = eta[3 * a + c];
+                    const double vr = (double)sv[3 * b + c].re, vi = (double)sv[3 * b + c].im;
+                    re += e.re * vr + e.im * vi;
+                    im += e.re * vi - e.im * vr;
+                }
+                acc[2 * (4 * a + b)] += re;
+                acc[2 * (4 * a + b) + 1] += im;
+            }
+    }
+    block_sum<32>(acc, red);
+    if (threadIdx.x == 0) {
+        double *out = C + ((int64_t)rhs * g.T + t) * 32;
+#pragma unroll
+        for (int k = 0; k < 32; ++k) out[k] = acc[k];
+    }
+}
+
+// loops[n][g][t] = sum_d sum_{ab} Gamma_g[a][b] C[n*ncls + d][t][a][b]
+__global__ void gamma_contract_kernel(const double *C, int ncls, int T, const double *gam, const int *gidx,
+                                      int n_gamma, double *loops)
+{
+    const int n = blockIdx.x;
+    for (int k = threadIdx.x; k < n_gamma * T; k += blockDim.x) {
+        const int gi = k / T, t = k - gi * T;
+        const double *G = gam + gidx[gi] * 32;
+        double re = 0, im = 0;
+        for (int d = 0; d < ncls; ++d) {
+            const double *c = C + (((int64_t)n * ncls + d) * T + t) * 32;
+            for (int ab = 0; ab < 16; ++ab) {
+                const double gr = G[2 * ab], gi2 = G[2 * ab + 1];
+                re += gr * c[2 * ab] - gi2 * c[2 * ab + 1];
+                im += gr * c[2 * ab + 1] + gi2 * c[2 * ab];
+            }
+        }
+        loops[(((int64_t)n * n_gamma + gi) * T + t) * 2] = re;
+        loops[(((int64_t)n * n_gamma + gi) * T + t) * 2 + 1] = im;
+    }
+}
+
+template <typename S>
+__global__ __launch_bounds__(BS) void links_convert_kernel(void *dst, int ne, const double *src64, int64_t Vh)
+{
+    using F = Fmt<S>;
+    using R = typename F::R;
+    const int64_t cb = (int64_t)blockIdx.x * BS + threadIdx.x;
+    const int mp = blockIdx.y;  // mu * 2 + parity
+    if (cb >= Vh) return;
+    const double2 *s = reinterpret_cast<const double2 *>(src64) + (int64_t)mp * 9 * Vh;
+    typename F::E *d = static_cast<typename F::E *>(dst) + (int64_t)mp * ne * Vh;
+    for (int e = 0; e < ne; ++e) {
+        double2 z = s[e * Vh + cb];
+        F::st(d, e * Vh + cb, cx<R>{R(z.x), R(z.y)});
+    }
+}
+
+#define DL_DISPATCH(prec, NAME, ...)                                                                    \
+    do {                                                                                                \
+        switch (prec) {                                                                                 \
+        case P64: hipLaunchKernelGGL(NAME<double>, __VA_ARGS__); break;                                 \
+        case P32: hipLaunchKernelGGL(NAME<float>, __VA_ARGS__); break;                                  \
+        case P16: hipLaunchKernelGGL(NAME<__half>, __VA_ARGS__); break;                                 \
+        default: hipLaunchKernelGGL(NAME<__hip_bfloat16>, __VA_ARGS__); break;                          \
+        }                                                                                               \
+    } while (0)
+
+double field_bytes(int prec, int64_t Vh, int nrhs)
+{
+    return ((double)Vh * 12 * elem_bytes(prec) + (prec == P16 ? 4.0 * Vh : 0.0)) * nrhs;
+}
+
+}  // namespace
+
+void k_pack(int prec, Field dst, int parity, const double *canon, const Geom &g, int nrhs, hipStream_t s)
+{
+    dim3 grid((g.Vh + BS - 1) / BS, nrhs);
+    DL_DISPATCH(prec, pack_kernel, grid, dim3(BS), 0, s, dst, parity, canon, g);
+}
+
+void k_unpack(int prec, Field src, int parity, double *canon, const Geom &g, int nrhs, hipStream_t s)
+{
+    dim3 grid((g.Vh + BS - 1) / BS, nrhs);
+    DL_DISPATCH(prec, unpack_kernel, grid, dim3(BS), 0, s, src, parity, canon, g);
+}
+
+void k_source(int prec, Field dst, int parity, const SourceSpec &src, const Geom &g, int nrhs, hipStream_t s)
+{
+    ProfScope ps(PROF_TRACE, field_bytes(prec, g.Vh, nrhs), s);
+    dim3 grid((g.Vh + BS - 1) / BS, nrhs);
+    DL_DISPATCH(prec, source_kernel, grid, dim3(BS), 0, s, dst, parity, src, g);
+}
+
+void k_trace(int prec, Field se, Field so, const SourceSpec &src, const Geom &g, int nrhs, double *C, hipStream_t s)
+{
+    ProfScope ps(PROF_TRACE, 2 * field_bytes(prec, g.Vh, nrhs), s);
+    dim3 grid(g.T, nrhs);
+    DL_DISPATCH(prec, trace_kernel, grid, dim3(BS), 0, s, se, so, src, g, C);
+}
+
+void k_gamma_contract(const double *C, int n_noise, int ncls, int T, const double *gam, const int *gidx,
+                      int n_gamma, double *loops, hipStream_t s)
+{
+    hipLaunchKernelGGL(gamma_contract_kernel, dim3(n_noise), dim3(128), 0, s, C, ncls, T, gam, gidx, n_gamma, loops);
+}
+
+void k_links_convert(int prec, void *dst, int ne, const double *src64, int64_t Vh, hipStream_t s)
+{
+    dim3 grid((Vh + BS - 1) / BS, 8);
+    DL_DISPATCH(prec, links_convert_kernel, grid, dim3(BS), 0, s, dst, ne, src64, Vh);
+}
+
+}  // namespace dl

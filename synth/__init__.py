@@ -53,12 +53,28 @@ def _reunitarise(u: np.ndarray) -> np.ndarray:
     return np.stack([r0, r1, r2], axis=-2)
 
 
+_CACHE: dict = {}
+
+
 def gauge_field(dims, eps: float, seed: int, chunk: int = 1 << 18) -> np.ndarray:
     """Seeded SU(3) field, complex128 array [4][V][3][3] (mu, site, row, col).
 
-    Sites are ordered x fastest: i = x + X*(y + Y*(z + Z*t)).
+    Sites are ordered x fastest: i = x + X*(y + Y*(z + Z*t)).  The result is
+    read-only and memoised per (dims, eps, seed) within the process.
     """
     dims = tuple(int(d) for d in dims)
+    key = (dims, float(eps), int(seed))
+    if key in _CACHE:
+        return _CACHE[key]
+    out = _gauge_field(dims, eps, seed, chunk)
+    out.flags.writeable = False
+    if len(_CACHE) > 8:
+        _CACHE.clear()
+    _CACHE[key] = out
+    return out
+
+
+def _gauge_field(dims, eps, seed, chunk):
     V = int(np.prod(dims))
     rng = np.random.default_rng(seed)
     lam = gell_mann()

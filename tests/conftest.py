@@ -29,3 +29,16 @@ def dl():
 
     pkg.load()
     return pkg
+
+
+def pytest_sessionstart(session):
+    """Build the in-tree libraries only when nothing is built yet."""
+    import importlib.util
+
+    lib = os.path.join(ROOT, "paper_1012_5168_amd", "libdloops.so")
+    if not os.path.exists(lib):
+        spec = importlib.util.spec_from_file_location("_dl_build", os.path.join(ROOT, "paper_1012_5168_amd",
+                                                                                "_build.py"))
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+        mod.build()

@@ -1,0 +1,88 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function that include/dloops.h declares, and rejects invalid arguments
+before any device work.  Also checks that the product package never reaches
+the oracle."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dloops.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^[A-Za-z_][\w \*]*?\b(dl_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_api():
+    names = declared_functions()
+    for required in ("dl_lattice_create", "dl_gauge_create", "dl_apply", "dl_solve", "dl_loops", "dl_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(dl):
+    lib = dl.load()
+    out = subprocess.run(["nm", "-D", "--defined-only", dl.LIBRARY_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (dl_\w+)", out))
+    for name in declared_functions():
+        assert name in exported, name
+        assert hasattr(lib, name)
+        assert name in dl.exported_symbols(), name
+
+
+def test_lattice_argument_validation(dl):
+    h = dl.dl_lattice_create((4, 4, 4, 8), 1)
+    assert dl.load().dl_lattice_volume(h) == 512
+    dl.dl_lattice_destroy(h)
+    for bad in [(3, 4, 4, 4), (4, 4, 0, 4), (4, -2, 4, 4), (4, 4, 4, 5)]:
+        with pytest.raises(dl.DLError) as e:
+            dl.dl_lattice_create(bad, 1)
+        assert e.value.code == dl.DL_EINVAL
+        assert "even" in str(e.value)
+    # null output pointer
+    import ctypes
+
+    d = (ctypes.c_int32 * 4)(4, 4, 4, 4)
+    assert dl.load().dl_lattice_create(d, 1, None) == dl.DL_EINVAL
+
+
+def test_sources_count_and_validation(dl):
+    h = dl.dl_lattice_create((4, 4, 4, 4), 1)
+    assert dl.dl_sources_count(h, dl.z2_sources(1, 16)) == 16
+    assert dl.dl_sources_count(h, dl.z2_sources(1, 24, scheme=dl.DL_DIL_SPIN_COLOUR)) == 288
+    assert dl.dl_sources_count(h, dl.z2_sources(1, 8, scheme=dl.DL_DIL_SPIN_COLOUR | dl.DL_DIL_CUBIC)) == 768
+    assert dl.dl_sources_count(h, dl.point_sources(0)) == 12
+    for bad in [dl.z2_sources(1, 0), dl.z2_sources(1, 2, scheme=8), dl.point_sources(256),
+                dl.dl_sources(dl.DL_SRC_POINT, 0, 0, 0, 2, 0), dl.dl_sources(7, 0, 0, 0, 1, 0)]:
+        with pytest.raises(dl.DLError) as e:
+            dl.dl_sources_count(h, bad)
+        assert e.value.code == dl.DL_EINVAL
+    dl.dl_lattice_destroy(h)
+
+
+def test_null_handles_rejected(dl):
+    lib = dl.load()
+    p = dl.solve_params()
+    assert lib.dl_solve(None, 0.1, p, None, None, 1, None, None) == dl.DL_EINVAL
+    assert lib.dl_apply(None, 0.1, 0, 0, None, None, 1, None) == dl.DL_EINVAL
+    assert "null" in dl.dl_last_error()
+    assert lib.dl_gauge_create(None, None, 1, 12, None, None) == dl.DL_EINVAL
+    assert lib.dl_profile_read(7, None, None) == dl.DL_EINVAL
+
+
+def test_product_never_reaches_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1012_5168_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".hpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "liboracle" not in text and "wilson_oracle" not in text, f
+    lib = os.path.join(pkg, "libdloops.so")
+    if os.path.exists(lib):
+        deps = subprocess.run(["readelf", "-d", lib], capture_output=True, text=True).stdout
+        assert "oracle" not in deps
