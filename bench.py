@@ -128,11 +128,13 @@ def main():
     n_d, ms_d, by_d = dl.dl_profile_read(0)
     n_b, ms_b, by_b = dl.dl_profile_read(1)
     n_t, ms_t, by_t = dl.dl_profile_read(2)
+    n_p, ms_p, by_p = dl.dl_profile_read(3)
     dl.dl_profile_enable(False)
     assert all(s[0] == dl.DL_OK for s in st), "a solve did not converge"
 
     ms_step = elapsed / args.steps * 1e3
     dslash_gbs = by_d / (ms_d * 1e-3) / 1e9
+    plain_gbs = by_p / (ms_p * 1e-3) / 1e9
     out = {
         "metric": "dslash HBM GB/s; time per loop at fixed stat. error vs plain FP64 solver",
         "value": round(dslash_gbs, 1),
@@ -162,12 +164,16 @@ def main():
         },
         "dslash_launches_per_step": n_d // args.steps,
         "roofline": {
+            "kernel": "dslash_kernel<double,6,false,0,*> (plain half dslash D_oe, FP64, 12-parameter links)",
             "bound": "hbm",
-            "achieved": round(dslash_gbs, 1),
+            "achieved": round(plain_gbs, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(dslash_gbs / HBM_PEAK_GBS, 4),
+            "frac": round(plain_gbs / HBM_PEAK_GBS, 4),
             "traffic": None,
+            "launches": n_p,
+            "avg_launch_us": round(ms_p / max(n_p, 1) * 1e3, 1),
+            "algorithmic_bytes_per_launch": round(by_p / max(n_p, 1)),
         },
     }
     if not args.no_cpu_baseline:

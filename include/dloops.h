@@ -192,6 +192,57 @@ typedef struct {
 int dl_loops(dl_gauge g, double kappa, const dl_sources *src, const dl_solve_params *params,
              const int32_t *gammas, int32_t n_gamma, double *loops, dl_solve_stats *stats, void *stream);
 
+/* Truncated solver method split (Section 2). */
+typedef struct {
+    int32_t n_lp;        /* noises first_noise .. first_noise + n_lp - 1: low-precision set */
+    int32_t n_hp;        /* the next n_hp noises: high-precision correction set */
+    dl_solve_params lp;  /* the truncated low-precision solve (e.g. DL_CGNR, DL_F16, fixed_iters 25) */
+    dl_solve_params hp;  /* the high-precision solve (e.g. DL_BICGSTAB, DL_F32 with FP64 reliable updates, 1e-10) */
+} dl_tsm;
+
+/*
+ * Truncated solver method (Section 2): low-precision solves on all
+ * n_lp + n_hp noises of src (src->n_noise must equal n_lp + n_hp) and
+ * high-precision solves on the n_hp correction noises.  loops: host double
+ * [n_lp + 2 n_hp][n_gamma][T][2] holding, per noise as in dl_loops, first the
+ * LP-set low-precision loops, then the HP-set high-precision loops, then the
+ * HP-set low-precision loops.  The estimate is mean(LP set, low) +
+ * mean(HP set, high - low); it and its variance are formed by the caller in
+ * FP64.  stats: host [(n_lp + n_hp) * classes + n_hp * classes] (the
+ * low-precision solves, then the high-precision ones) or NULL.
+ */
+int dl_loops_tsm(dl_gauge g, double kappa, const dl_sources *src, const dl_tsm *tsm, const int32_t *gammas,
+                 int32_t n_gamma, double *loops, dl_solve_stats *stats, void *stream);
+
+/*
+ * Derivative of the loop estimator with respect to kappa: since
+ * dM^-1/dkappa = M^-1 D M^-1, dloops[n][g][t] = sum_d eta_d^+ P_t Gamma u_d with
+ * u_d = M^-1 D M^-1 eta_d (two solves per right-hand side, tolerance-driven
+ * BiCGStab only).  dloops: host double [n_noise][n_gamma][T][2].  stats: host
+ * [2][n_noise * classes] (first and second solves) or NULL.
+ */
+int dl_loops_dkappa(dl_gauge g, double kappa, const dl_sources *src, const dl_solve_params *params,
+                    const int32_t *gammas, int32_t n_gamma, double *dloops, dl_solve_stats *stats, void *stream);
+
+/*
+ * Gradient of the real functional F = Re sum_{n,g,t} conj(w[n][g][t]) loops[n][g][t]
+ * with respect to the gauge links, each U_mu(x) taken as an unconstrained 3x3
+ * complex matrix: grad[mu][x][a][b] = dF/dRe U_ab + i dF/dIm U_ab (so
+ * dF = Re sum conj(grad) dU).  With s = M^-1 eta and the adjoint solution
+ * a = M^-dagger (sum_g w Gamma_g^+ P_t eta) = gamma5 M^-1 gamma5 (...), the
+ * variation is dF = Re kappa sum a^+ dD s (two solves per right-hand side,
+ * tolerance-driven BiCGStab only).  w: host double [n_noise][n_gamma][T][2]
+ * (the cotangent of the loops).  grad: host double [4][V][3][3][2]
+ * (overwritten).  loops: host [n_noise][n_gamma][T][2] or NULL (the forward
+ * loops, as dl_loops).  dloops: host [n_noise][n_gamma][T][2] or NULL (the
+ * kappa derivative, as dl_loops_dkappa, at the cost of a third solve).
+ * stats: host [2 or 3][n_noise * classes] (forward, adjoint, kappa solves) or
+ * NULL.
+ */
+int dl_loops_link_grad(dl_gauge g, double kappa, const dl_sources *src, const dl_solve_params *params,
+                       const int32_t *gammas, int32_t n_gamma, const double *w, double *grad, double *loops,
+                       double *dloops, dl_solve_stats *stats, void *stream);
+
 /* Number of right-hand sides (solves) a dl_sources description expands to, or < 0 if invalid. */
 int64_t dl_sources_count(dl_lattice lat, const dl_sources *src);
 
@@ -203,10 +254,19 @@ int64_t dl_sources_count(dl_lattice lat, const dl_sources *src);
  */
 int dl_sources_fill(dl_lattice lat, const dl_sources *src, int64_t first_rhs, int64_t nrhs, void *out, void *stream);
 
-/* Time spent in the library's kernels since profiling was enabled.  kind:
-   0 = hopping (dslash) kernels, 1 = Krylov vector kernels, 2 = sources and
-   traces.  Returns launches; *ms = summed event-timed duration, *bytes = the
-   algorithmic bytes of those launches (each operand moved once). */
+/*
+ * Kernel profiling on the library's streams.  dl_profile_enable(1) resets the
+ * counters and brackets every following launch with HIP events (and a device
+ * counter of the right-hand sides a hopping launch actually processed);
+ * dl_profile_enable(0) stops.  Not for use while a stream is being captured.
+ * dl_profile_read(kind, ms, bytes) synchronises and returns the number of
+ * launches of that kind, their summed event-timed duration and their
+ * algorithmic bytes (every operand moved once; for the hopping kernel, the
+ * links once per launch plus the in/out/epilogue half spinors of each live
+ * right-hand side).  kind: 0 = all hopping kernels, 1 = Krylov vector
+ * kernels, 2 = sources and traces, 3 = the plain (no epilogue, not adjoint)
+ * hopping kernel.  Returns DL_EINVAL for another kind.
+ */
 int dl_profile_enable(int32_t on);
 int64_t dl_profile_read(int32_t kind, double *ms, double *bytes);
 

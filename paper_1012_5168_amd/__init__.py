@@ -67,6 +67,15 @@ class dl_solve_stats(ctypes.Structure):
     ]
 
 
+class dl_tsm(ctypes.Structure):
+    _fields_ = [
+        ("n_lp", ctypes.c_int32),
+        ("n_hp", ctypes.c_int32),
+        ("lp", dl_solve_params),
+        ("hp", dl_solve_params),
+    ]
+
+
 class dl_sources(ctypes.Structure):
     _fields_ = [
         ("kind", ctypes.c_int32),
@@ -92,6 +101,14 @@ _SIGNATURES = {
                                 ctypes.POINTER(dl_solve_stats), _P]),
     "dl_loops": (ctypes.c_int, [_P, ctypes.c_double, ctypes.POINTER(dl_sources), ctypes.POINTER(dl_solve_params), _P,
                                 ctypes.c_int32, _P, ctypes.POINTER(dl_solve_stats), _P]),
+    "dl_loops_tsm": (ctypes.c_int, [_P, ctypes.c_double, ctypes.POINTER(dl_sources), ctypes.POINTER(dl_tsm), _P,
+                                    ctypes.c_int32, _P, ctypes.POINTER(dl_solve_stats), _P]),
+    "dl_loops_dkappa": (ctypes.c_int, [_P, ctypes.c_double, ctypes.POINTER(dl_sources),
+                                       ctypes.POINTER(dl_solve_params), _P, ctypes.c_int32, _P,
+                                       ctypes.POINTER(dl_solve_stats), _P]),
+    "dl_loops_link_grad": (ctypes.c_int, [_P, ctypes.c_double, ctypes.POINTER(dl_sources),
+                                          ctypes.POINTER(dl_solve_params), _P, ctypes.c_int32, _P, _P, _P, _P,
+                                          ctypes.POINTER(dl_solve_stats), _P]),
     "dl_sources_count": (ctypes.c_int64, [_P, ctypes.POINTER(dl_sources)]),
     "dl_sources_fill": (ctypes.c_int, [_P, ctypes.POINTER(dl_sources), ctypes.c_int64, ctypes.c_int64, _P, _P]),
     "dl_profile_enable": (ctypes.c_int, [ctypes.c_int32]),
@@ -196,6 +213,35 @@ def dl_loops(gauge, kappa, sources, params, gammas, loops_out: np.ndarray, stats
     return rc
 
 
+def dl_loops_tsm(gauge, kappa, sources, tsm, gammas, loops_out: np.ndarray, stats=None, stream=None):
+    g = np.ascontiguousarray(np.asarray(gammas, dtype=np.int32))
+    rc = load().dl_loops_tsm(gauge, float(kappa), ctypes.byref(sources), ctypes.byref(tsm), g.ctypes.data_as(_P),
+                             len(g), loops_out.ctypes.data_as(_P), stats, _stream(stream))
+    _check(rc, allow=(DL_ENOCONV,))
+    return rc
+
+
+def dl_loops_dkappa(gauge, kappa, sources, params, gammas, dloops_out: np.ndarray, stats=None, stream=None):
+    g = np.ascontiguousarray(np.asarray(gammas, dtype=np.int32))
+    rc = load().dl_loops_dkappa(gauge, float(kappa), ctypes.byref(sources), ctypes.byref(params),
+                                g.ctypes.data_as(_P), len(g), dloops_out.ctypes.data_as(_P), stats, _stream(stream))
+    _check(rc, allow=(DL_ENOCONV,))
+    return rc
+
+
+def dl_loops_link_grad(gauge, kappa, sources, params, gammas, w: np.ndarray, grad_out: np.ndarray,
+                       loops_out: np.ndarray | None = None, dloops_out: np.ndarray | None = None, stats=None,
+                       stream=None):
+    g = np.ascontiguousarray(np.asarray(gammas, dtype=np.int32))
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    ptr = lambda a: None if a is None else a.ctypes.data_as(_P)  # noqa: E731
+    rc = load().dl_loops_link_grad(gauge, float(kappa), ctypes.byref(sources), ctypes.byref(params),
+                                   g.ctypes.data_as(_P), len(g), w.ctypes.data_as(_P), grad_out.ctypes.data_as(_P),
+                                   ptr(loops_out), ptr(dloops_out), stats, _stream(stream))
+    _check(rc, allow=(DL_ENOCONV,))
+    return rc
+
+
 def dl_sources_count(lat, sources) -> int:
     n = load().dl_sources_count(lat, ctypes.byref(sources))
     if n < 0:
@@ -294,3 +340,64 @@ def loops(gauge: Gauge, kappa: float, sources: dl_sources, gammas, params=None, 
     dl_loops(gauge.h, kappa, sources, params, gammas, buf, st, stream)
     stats = [(s.status, s.iters, s.reliable_updates, s.true_rel_residual) for s in st]
     return buf[..., 0] + 1j * buf[..., 1], stats
+
+
+def _stats_list(st):
+    return [(s.status, s.iters, s.reliable_updates, s.true_rel_residual) for s in st]
+
+
+def loops_tsm(gauge: Gauge, kappa: float, sources: dl_sources, n_lp: int, n_hp: int, gammas, lp_params, hp_params,
+              stream=None):
+    """Truncated solver method: returns (lp_set_lp, hp_set_hp, hp_set_lp, stats), each complex
+    [n][n_gamma][T]; the estimate is mean(lp_set_lp) + mean(hp_set_hp - hp_set_lp)."""
+    T = gauge.lattice.dims[3]
+    buf = np.zeros((n_lp + 2 * n_hp, len(gammas), T, 2), dtype=np.float64)
+    ncls = dl_sources_count(gauge.lattice.h, sources) // int(sources.n_noise)
+    st = (dl_solve_stats * ((n_lp + 2 * n_hp) * ncls))()
+    dl_loops_tsm(gauge.h, kappa, sources, dl_tsm(n_lp, n_hp, lp_params, hp_params), gammas, buf, st, stream)
+    z = buf[..., 0] + 1j * buf[..., 1]
+    return z[:n_lp], z[n_lp:n_lp + n_hp], z[n_lp + n_hp:], _stats_list(st)
+
+
+def tsm_estimate(lp_set_lp, hp_set_hp, hp_set_lp):
+    """The truncated solver method's estimate and its variance (FP64, host)."""
+    lp_set_lp, hp_set_hp, hp_set_lp = (np.asarray(a, dtype=np.complex128) for a in (lp_set_lp, hp_set_hp, hp_set_lp))
+    corr = hp_set_hp - hp_set_lp
+    est = lp_set_lp.mean(axis=0) + corr.mean(axis=0)
+    var = lp_set_lp.var(axis=0, ddof=1) / len(lp_set_lp) + corr.var(axis=0, ddof=1) / len(corr)
+    return est, var
+
+
+def loops_dkappa(gauge: Gauge, kappa: float, sources: dl_sources, gammas, params=None, stream=None):
+    """d/dkappa of the per-noise loop estimates, complex [n_noise][n_gamma][T]."""
+    params = params or solve_params()
+    T = gauge.lattice.dims[3]
+    buf = np.zeros((int(sources.n_noise), len(gammas), T, 2), dtype=np.float64)
+    nrhs = dl_sources_count(gauge.lattice.h, sources)
+    st = (dl_solve_stats * (2 * nrhs))()
+    dl_loops_dkappa(gauge.h, kappa, sources, params, gammas, buf, st, stream)
+    return buf[..., 0] + 1j * buf[..., 1], _stats_list(st)
+
+
+def loops_link_grad(gauge: Gauge, kappa: float, sources: dl_sources, gammas, w, params=None, with_dkappa=False,
+                    stream=None):
+    """Gradient of Re sum conj(w[n][g][t]) L[n][g][t] with respect to the links, complex [4][V][3][3]
+    (dF = Re sum conj(grad) dU); w is [n_noise][n_gamma][T] (or [n_gamma][T], the same for every
+    noise).  Returns (grad, loops, dloops or None, stats)."""
+    params = params or solve_params()
+    T = gauge.lattice.dims[3]
+    V = gauge.lattice.V
+    n = int(sources.n_noise)
+    w = np.asarray(w, dtype=np.complex128)
+    if w.ndim == 2:
+        w = np.broadcast_to(w, (n,) + w.shape)
+    w = w.reshape(n, len(gammas), T)
+    wb = np.stack([w.real, w.imag], axis=-1)
+    grad = np.zeros((4, V, 3, 3, 2), dtype=np.float64)
+    loops = np.zeros((n, len(gammas), T, 2), dtype=np.float64)
+    dk = np.zeros((n, len(gammas), T, 2), dtype=np.float64) if with_dkappa else None
+    nrhs = dl_sources_count(gauge.lattice.h, sources)
+    st = (dl_solve_stats * (3 * nrhs))()
+    dl_loops_link_grad(gauge.h, kappa, sources, params, gammas, wb, grad, loops, dk, st, stream)
+    z = lambda a: None if a is None else a[..., 0] + 1j * a[..., 1]  # noqa: E731
+    return z(grad), z(loops), z(dk), _stats_list(st)

@@ -91,15 +91,34 @@ Field HalfField::view_rhs(int64_t r) const
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
 struct ProfRec {
-    int kind;
+    int kind, kind2;
     double bytes;
     hipEvent_t e0, e1;
+    int slot;  // counter slot or -1
+    double unit_bytes, fixed_bytes, units_div;
 };
 static std::vector<ProfRec> g_prof_pending;
 static double g_prof_ms[PROF_NKIND], g_prof_bytes[PROF_NKIND];
 static int64_t g_prof_n[PROF_NKIND];
+static DevBuf g_prof_ctr;  // device counters, one per profiled hopping launch
+static int g_prof_next = 0;
+static const int PROF_SLOTS = 1 << 16;
 
-ProfScope::ProfScope(int kind_, double bytes_, hipStream_t s_) : kind(kind_), bytes(bytes_), s(s_)
+static void prof_drain_locked();
+
+bool prof_on() { return g_prof_on; }
+
+unsigned *prof_counter()
+{
+    if (!g_prof_on) return nullptr;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_ctr.p) return nullptr;
+    if (g_prof_next >= PROF_SLOTS) prof_drain_locked();
+    return g_prof_ctr.as<unsigned>() + g_prof_next++;
+}
+
+ProfScope::ProfScope(int kind_, double bytes_, hipStream_t s_, int kind2_)
+    : kind(kind_), kind2(kind2_), bytes(bytes_), s(s_)
 {
     if (!g_prof_on) return;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -114,23 +133,48 @@ ProfScope::~ProfScope()
     if (!e0) return;
     (void)hipEventRecord(e1, s);
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    g_prof_pending.push_back({kind, bytes, e0, e1});
+    int slot = counter ? (int)(counter - g_prof_ctr.as<unsigned>()) : -1;
+    g_prof_pending.push_back({kind, kind2, bytes, e0, e1, slot, unit_bytes, fixed_bytes, units_div});
 }
 
-static void prof_drain()
+static void prof_drain_locked()
 {
-    std::lock_guard<std::mutex> lk(g_prof_mu);
+    std::vector<unsigned> ctr;
+    if (g_prof_ctr.p && g_prof_next > 0) {
+        (void)hipDeviceSynchronize();
+        ctr.resize(g_prof_next);
+        (void)hipMemcpy(ctr.data(), g_prof_ctr.p, sizeof(unsigned) * g_prof_next, hipMemcpyDeviceToHost);
+    }
     for (auto &r : g_prof_pending) {
         float ms = 0;
         if (hipEventSynchronize(r.e1) == hipSuccess && hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) {
-            g_prof_ms[r.kind] += ms;
-            g_prof_bytes[r.kind] += r.bytes;
-            g_prof_n[r.kind] += 1;
+            double by = r.bytes;
+            if (r.slot >= 0 && r.slot < (int)ctr.size()) {
+                const double units = ctr[r.slot];
+                by = (units > 0 ? r.fixed_bytes : 0.0) + r.unit_bytes * units / r.units_div;
+            }
+            for (int k : {r.kind, r.kind2}) {
+                if (k < 0) continue;
+                g_prof_ms[k] += ms;
+                g_prof_bytes[k] += by;
+                g_prof_n[k] += 1;
+            }
         }
         (void)hipEventDestroy(r.e0);
         (void)hipEventDestroy(r.e1);
     }
     g_prof_pending.clear();
+    if (g_prof_ctr.p && g_prof_next > 0) {
+        (void)hipMemset(g_prof_ctr.p, 0, sizeof(unsigned) * PROF_SLOTS);
+        (void)hipDeviceSynchronize();
+    }
+    g_prof_next = 0;
+}
+
+static void prof_drain()
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_drain_locked();
 }
 
 // ====================================================================== dslash launch
@@ -140,42 +184,49 @@ int dslash_site_blocks(const Geom &g, int /*prec*/, int /*nrhs*/) { return (g.Vh
 template <typename S>
 void launch_dslash_t(const DslashCall &c, int nr, int bs, hipStream_t s);
 
-// algorithmic bytes of one launch: every operand moved once
-static double dslash_bytes(const DslashCall &c)
+// algorithmic bytes of one launch: every operand moved once.  Per live
+// right-hand side: the input half spinor, the output and the epilogue
+// operands; once per launch: the links.
+static void dslash_bytes(const DslashCall &c, double &per_rhs, double &links)
 {
     const double vh = c.g.Vh, e = (double)elem_bytes(c.prec), nrm = c.prec == P16 ? 4.0 : 0.0;
-    const double field = vh * (12 * e + nrm) * c.nrhs;
-    const double links = vh * 8.0 * (c.recon == 12 ? 6 : 9) * e;
+    const double field = vh * (12 * e + nrm);
+    links = vh * 8.0 * (c.recon == 12 ? 6 : 9) * e;
     int nfield = 2;  // in, out
-    if (c.epi != EPI_PLAIN) nfield += 1;                                        // x
-    if (c.epi == EPI_XPAY_DOT || c.epi == EPI_XMY_NRM) nfield += 1;             // y
-    return nfield * field + links;
+    if (c.epi != EPI_PLAIN) nfield += 1;                             // x
+    if (c.epi == EPI_XPAY_DOT || c.epi == EPI_XMY_NRM) nfield += 1;  // y
+    per_rhs = nfield * field;
 }
 
-struct TuneChoice {
-    int nr, bs;
-};
-TuneChoice tune_lookup(const DslashCall &c, hipStream_t s);
-
-int launch_dslash(const DslashCall &c, hipStream_t s)
+void launch_dslash_any(const DslashCall &c, int nr, int bs, hipStream_t s)
 {
-    TuneChoice t = tune_lookup(c, s);
-    ProfScope ps(PROF_DSLASH, dslash_bytes(c), s);
     switch (c.prec) {
-    case P64: launch_dslash_t<double>(c, t.nr, t.bs, s); break;
-    case P32: launch_dslash_t<float>(c, t.nr, t.bs, s); break;
-    case P16: launch_dslash_t<__half>(c, t.nr, t.bs, s); break;
-    default: launch_dslash_t<__hip_bfloat16>(c, t.nr, t.bs, s); break;
+    case P64: launch_dslash_t<double>(c, nr, bs, s); break;
+    case P32: launch_dslash_t<float>(c, nr, bs, s); break;
+    case P16: launch_dslash_t<__half>(c, nr, bs, s); break;
+    default: launch_dslash_t<__hip_bfloat16>(c, nr, bs, s); break;
     }
-    return (c.g.Vh + t.bs - 1) / t.bs;
 }
 
-// default launch configuration (the autotuner refines it when enabled)
-TuneChoice tune_lookup(const DslashCall &c, hipStream_t)
+int launch_dslash(const DslashCall &c0, hipStream_t s)
 {
-    (void)c;
-    return TuneChoice{1, 256};
+    const TuneChoice t = tune_lookup(c0, s);
+    DslashCall c = c0;
+    double per_rhs, links;
+    dslash_bytes(c, per_rhs, links);
+    const int nblk = (c.g.Vh + t.bs - 1) / t.bs;
+    c.live_count = prof_counter();
+    {
+        ProfScope ps(PROF_DSLASH, per_rhs * c.nrhs + links, s, (c.epi == EPI_PLAIN && !c.dag) ? PROF_DSLASH_PLAIN : -1);
+        ps.counter = c.live_count;
+        ps.unit_bytes = per_rhs;
+        ps.fixed_bytes = links;
+        ps.units_div = nblk;
+        launch_dslash_any(c, t.nr, t.bs, s);
+    }
+    return nblk;
 }
+
 
 }  // namespace dl
 
@@ -538,7 +589,7 @@ void bicgstab_batch(const Ctx &c, double kappa, const dl_solve_params &prm, Solv
     const int poll = parse_poll(prm);
     std::vector<int> h;
     int it = 0;
-    const int cap = prm.maxiter + 8;
+    const int cap = prm.maxiter + poll + 8;
     while (it < cap) {
         for (int k = 0; k < poll; ++k, ++it) {
             k_bicg_p(P, w.p.view(), w.r.view(), w.v.view(), st, act, Vh, n, c.s);
@@ -557,24 +608,29 @@ void bicgstab_batch(const Ctx &c, double kappa, const dl_solve_params &prm, Solv
             k_bicg_omega(st, act, n, parts, nbd, c.s);
             k_bicg_xr(P, xit, w.r.view(), w.p.view(), w.t.view(), w.rh.view(), st, act, Vh, n, parts, c.s);
             k_bicg_rho(st, act, upd, nullptr, n, parts, nb, 3, 0, mixed, c.s);
-            // reliable update / convergence check for the flagged right-hand sides:
-            // fold the iterate, recompute r = bhat - Mhat x in FP64
+        }
+        DL_HIP(hipGetLastError());
+        // Poll point.  Right-hand sides flagged for a reliable update (converged,
+        // out of iterations, or |r| dropped by delta) get their iterate folded
+        // into the FP64 x and the FP64 residual bhat - Mhat x recomputed; where
+        // the true residual disagrees with a claimed convergence the recursion
+        // restarts from it.
+        if (count_host(w.upd, n, c.s, h) > 0) {
             if (mixed) k_fold_x(w.x64.view(), P, w.xlo.view(), Vh, n, upd, c.s);
             launch_dslash(
-                dcall(c, P64, 1, false, EPI_PLAIN, w.x64.view(), w.tmp64.view(), NOF, NOF, 1.0, n, nullptr, upd), c.s);
+                dcall(c, P64, 1, false, EPI_PLAIN, w.x64.view(), w.tmp64.view(), NOF, NOF, 1.0, n, nullptr, upd),
+                c.s);
             int nb64 = launch_dslash(dcall(c, P64, 0, false, EPI_XMY_NRM, w.tmp64.view(), w.r64.view(), w.bhat.view(),
                                            w.x64.view(), k2, n, parts2, upd),
                                      c.s);
             k_copy(P, w.r.view(), P64, w.r64.view(), Vh, n, upd, c.s);
             k_true_residual(st, act, upd, rst, n, parts2, nullptr, nb64, 0, c.s);
-            // restart the recursion where the true residual disagreed with the iterated one
             k_copy(P, w.rh.view(), P, w.r.view(), Vh, n, rst, c.s);
             k_zero(P, w.p.view(), Vh, n, rst, c.s);
             k_zero(P, w.v.view(), Vh, n, rst, c.s);
             k_dot_parts(P, w.rh.view(), w.r.view(), Vh, n, rst, parts, c.s);
             k_bicg_rho(st, act, upd, rst, n, parts, nb, 2, 1, mixed, c.s);
         }
-        DL_HIP(hipGetLastError());
         if (count_host(w.act, n, c.s, h) == 0) break;
     }
     // x_o = b_o + kappa D_oe x_e
@@ -839,90 +895,282 @@ extern "C" int dl_sources_fill(dl_lattice lat, const dl_sources *src, int64_t fi
     });
 }
 
+namespace {
+
+enum LoopMode { MODE_LOOPS = 0, MODE_DKAPPA = 1, MODE_GRAD = 2 };
+
+void validate_gammas(const int32_t *gammas, int32_t n_gamma)
+{
+    DL_REQUIRE(gammas != nullptr, "gammas: null pointer");
+    DL_REQUIRE(n_gamma >= 1 && n_gamma <= 16, "n_gamma must be in [1, 16]");
+    for (int i = 0; i < n_gamma; ++i) DL_REQUIRE(gammas[i] >= 0 && gammas[i] <= 15, "gamma index outside [0, 15]");
+}
+
+// A[n][t] = gamma5 sum_g W[n][g][t] Gamma_g^+ for every noise and timeslice, [n][T][4][4] complex
+std::vector<double> adjoint_matrices(const std::vector<double> &gtab, const int32_t *gammas, int n_gamma,
+                                     const double *W, int T, int n_noise)
+{
+    std::vector<double> A((size_t)n_noise * T * 32, 0.0);
+    const double g5[4] = {1, 1, -1, -1};
+    for (int n = 0; n < n_noise; ++n)
+        for (int t = 0; t < T; ++t)
+            for (int gi = 0; gi < n_gamma; ++gi) {
+                const double *w = W + (((size_t)n * n_gamma + gi) * T + t) * 2;
+                const double wr = w[0], wi = w[1];
+                const double *G = gtab.data() + gammas[gi] * 32;
+                double *At = A.data() + ((size_t)n * T + t) * 32;
+                for (int a = 0; a < 4; ++a)
+                    for (int b = 0; b < 4; ++b) {
+                        // (Gamma^+)_{ab} = conj(Gamma_{ba})
+                        const double gr = G[2 * (4 * b + a)], gim = -G[2 * (4 * b + a) + 1];
+                        At[2 * (4 * a + b)] += g5[a] * (wr * gr - wi * gim);
+                        At[2 * (4 * a + b) + 1] += g5[a] * (wr * gim + wi * gr);
+                    }
+            }
+    return A;
+}
+
+// The loop estimator and its derivatives over a batch loop of whole noises.
+//   MODE_LOOPS:  out[n][g][t] = sum_d eta^+ P_t Gamma s, s = M^-1 eta
+//   MODE_DKAPPA: out[n][g][t] = sum_d eta^+ P_t Gamma u, u = M^-1 D M^-1 eta
+//   MODE_GRAD:   grad += d/dU of Re sum conj(W[n]) L[n], using s and the adjoint
+//                a = gamma5 M^-1 gamma5 (sum_g W[n] Gamma^+ P_t eta); out (the
+//                forward loops) may be null; dout, if set, receives the kappa
+//                derivative as in MODE_DKAPPA (a third solve)
+// stats: per right-hand side and solve ([nsolve][nrhs]) or null.
+int loops_run(dl_gauge G, double kappa, const dl_sources *src, const dl_solve_params &prm, const int32_t *gammas,
+              int n_gamma, int mode, const double *W, double *out_host, double *grad_host, dl_solve_stats *stats,
+              hipStream_t stream, double *dout_host = nullptr)
+{
+    Ctx c{G, G->lat.geom(), stream};
+    const int64_t Vh = G->lat.Vh, V = G->lat.V;
+    const int T = c.g.T;
+    const int ncls = source_classes(src);
+    const bool cg = prm.solver == DL_CGNR;
+    size_t per = (cg ? SolveWork::bytes_cgnr(prm.prec, Vh) : SolveWork::bytes_bicg(prm.prec, Vh)) +
+                 (size_t)T * 32 * 8 + 16;
+    if (mode == MODE_GRAD) per += 2 * (size_t)Vh * 12 * 16;  // the stored forward solution
+    const int64_t total = (int64_t)src->n_noise * ncls;
+    const int nsolve = mode == MODE_LOOPS ? 1 : (mode == MODE_GRAD && dout_host) ? 3 : 2;
+    const int B = batch_size(per, total, ncls);
+    std::vector<double> gtab = gamma_table();
+    DevBuf dgam(gtab.size() * sizeof(double)), dgidx(sizeof(int) * n_gamma), dA, dgrad;
+    DevBuf dloops((size_t)src->n_noise * n_gamma * T * 2 * sizeof(double)), ddk;
+    if (dout_host) ddk.alloc(dloops.bytes);
+    DL_HIP(hipMemcpyAsync(dgam.p, gtab.data(), dgam.bytes, hipMemcpyHostToDevice, c.s));
+    DL_HIP(hipMemcpyAsync(dgidx.p, gammas, dgidx.bytes, hipMemcpyHostToDevice, c.s));
+    if (mode == MODE_GRAD) {
+        std::vector<double> A = adjoint_matrices(gtab, gammas, n_gamma, W, T, src->n_noise);
+        dA.alloc(A.size() * sizeof(double));
+        DL_HIP(hipMemcpyAsync(dA.p, A.data(), dA.bytes, hipMemcpyHostToDevice, c.s));
+        dgrad.alloc((size_t)4 * V * 9 * 16);
+        k_zero(P64, Field{dgrad.p, nullptr}, (int64_t)4 * V * 9 / 12, 1, nullptr, c.s);
+    }
+    int worst = DL_OK;
+    std::vector<int64_t> hnoise;
+    std::vector<int> hcls;
+    for (int64_t r0 = 0; r0 < total; r0 += B) {
+        const int n = (int)std::min<int64_t>(B, total - r0);
+        const int nn = n / ncls;
+        hnoise.resize(n);
+        hcls.resize(n);
+        for (int i = 0; i < n; ++i) {
+            hnoise[i] = src->first_noise + (r0 + i) / ncls;
+            hcls[i] = (int)((r0 + i) % ncls);
+        }
+        DevBuf dnoise(sizeof(int64_t) * n), dcls(sizeof(int) * n), dC((size_t)n * T * 32 * sizeof(double));
+        DL_HIP(hipMemcpyAsync(dnoise.p, hnoise.data(), dnoise.bytes, hipMemcpyHostToDevice, c.s));
+        DL_HIP(hipMemcpyAsync(dcls.p, hcls.data(), dcls.bytes, hipMemcpyHostToDevice, c.s));
+        SourceSpec ss;
+        ss.kind = src->kind;
+        ss.scheme = src->kind == DL_SRC_POINT ? 0 : src->scheme;
+        ss.seed = src->seed;
+        ss.V = V;
+        ss.point_site = src->point_site;
+        ss.noise = dnoise.as<int64_t>();
+        ss.cls = dcls.as<int>();
+        SolveWork w;
+        std::vector<std::vector<dl_solve_stats>> st(nsolve, std::vector<dl_solve_stats>(n));
+        int sol_prec = P64;
+        if (cg) {
+            w.alloc_cgnr(prm.prec, n, Vh);
+            k_source(prm.prec, w.be.view(), 0, ss, c.g, n, c.s);
+            k_source(prm.prec, w.bo.view(), 1, ss, c.g, n, c.s);
+            cgnr_batch(c, kappa, prm.fixed_iters, w);
+            sol_prec = prm.prec;
+            fill_stats(w, {}, st[0].data(), c.s, true);
+        } else {
+            std::vector<double> res2;
+            w.alloc_bicg(prm.prec, n, Vh);
+            k_source(P64, w.be.view(), 0, ss, c.g, n, c.s);
+            k_source(P64, w.bo.view(), 1, ss, c.g, n, c.s);
+            bicgstab_batch(c, kappa, prm, w);
+            if (stats) true_residual_full(c, kappa, w, res2);
+            fill_stats(w, res2, st[0].data(), c.s, false);
+            if (mode == MODE_DKAPPA) {
+                // second solve on w = D s (sources are regenerated for the trace)
+                launch_dslash(dcall(c, P64, 0, false, EPI_PLAIN, w.xo.view(), w.be.view(), NOF, NOF, 1.0, n, nullptr,
+                                    nullptr),
+                              c.s);
+                launch_dslash(dcall(c, P64, 1, false, EPI_PLAIN, w.x64.view(), w.bo.view(), NOF, NOF, 1.0, n,
+                                    nullptr, nullptr),
+                              c.s);
+                bicgstab_batch(c, kappa, prm, w);
+                res2.clear();
+                if (stats) true_residual_full(c, kappa, w, res2);
+                fill_stats(w, res2, st[1].data(), c.s, false);
+            } else if (mode == MODE_GRAD) {
+                HalfField se, so;
+                se.alloc(P64, n, Vh);
+                so.alloc(P64, n, Vh);
+                k_copy(P64, se.view(), P64, w.x64.view(), Vh, n, nullptr, c.s);
+                k_copy(P64, so.view(), P64, w.xo.view(), Vh, n, nullptr, c.s);
+                if (out_host) {
+                    k_trace(P64, se.view(), so.view(), ss, c.g, n, dC.as<double>(), c.s);
+                    k_gamma_contract(dC.as<double>(), nn, ncls, T, dgam.as<double>(), dgidx.as<int>(), n_gamma,
+                                     dloops.as<double>() + (r0 / ncls) * n_gamma * T * 2, c.s);
+                }
+                if (dout_host) {
+                    // kappa derivative: u = M^-1 D s
+                    launch_dslash(dcall(c, P64, 0, false, EPI_PLAIN, so.view(), w.be.view(), NOF, NOF, 1.0, n,
+                                        nullptr, nullptr),
+                                  c.s);
+                    launch_dslash(dcall(c, P64, 1, false, EPI_PLAIN, se.view(), w.bo.view(), NOF, NOF, 1.0, n,
+                                        nullptr, nullptr),
+                                  c.s);
+                    bicgstab_batch(c, kappa, prm, w);
+                    res2.clear();
+                    if (stats) true_residual_full(c, kappa, w, res2);
+                    fill_stats(w, res2, st[2].data(), c.s, false);
+                    k_trace(P64, w.x64.view(), w.xo.view(), ss, c.g, n, dC.as<double>(), c.s);
+                    k_gamma_contract(dC.as<double>(), nn, ncls, T, dgam.as<double>(), dgidx.as<int>(), n_gamma,
+                                     ddk.as<double>() + (r0 / ncls) * n_gamma * T * 2, c.s);
+                }
+                const double *Ab = dA.as<double>();
+                k_adjoint_source(w.be.view(), 0, ss, c.g, n, Ab, src->first_noise, c.s);
+                k_adjoint_source(w.bo.view(), 1, ss, c.g, n, Ab, src->first_noise, c.s);
+                bicgstab_batch(c, kappa, prm, w);
+                res2.clear();
+                if (stats) true_residual_full(c, kappa, w, res2);
+                fill_stats(w, res2, st[1].data(), c.s, false);
+                k_link_grad(se.view(), so.view(), w.x64.view(), w.xo.view(), c.g, n, kappa, dgrad.as<double>(),
+                            c.s);
+                DL_HIP(hipStreamSynchronize(c.s));
+            }
+        }
+        if (mode != MODE_GRAD) {
+            k_trace(sol_prec, w.x64.view(), w.xo.view(), ss, c.g, n, dC.as<double>(), c.s);
+            k_gamma_contract(dC.as<double>(), nn, ncls, T, dgam.as<double>(), dgidx.as<int>(), n_gamma,
+                             dloops.as<double>() + (r0 / ncls) * n_gamma * T * 2, c.s);
+        }
+        DL_HIP(hipGetLastError());
+        DL_HIP(hipStreamSynchronize(c.s));
+        for (int k = 0; k < nsolve; ++k)
+            for (int i = 0; i < n; ++i) {
+                if (stats) stats[(int64_t)k * total + r0 + i] = st[k][i];
+                if (st[k][i].status != DL_OK && worst == DL_OK) worst = st[k][i].status;
+            }
+    }
+    if (out_host) DL_HIP(hipMemcpyAsync(out_host, dloops.p, dloops.bytes, hipMemcpyDeviceToHost, c.s));
+    if (grad_host) DL_HIP(hipMemcpyAsync(grad_host, dgrad.p, dgrad.bytes, hipMemcpyDeviceToHost, c.s));
+    if (dout_host) DL_HIP(hipMemcpyAsync(dout_host, ddk.p, ddk.bytes, hipMemcpyDeviceToHost, c.s));
+    DL_HIP(hipStreamSynchronize(c.s));
+    if (worst != DL_OK) g_err = "at least one solve did not converge";
+    return worst;
+}
+
+void check_solver_for(dl_gauge G, const dl_solve_params &prm)
+{
+    check_prec(G, prm.prec);
+    if (prm.solver == DL_BICGSTAB) check_prec(G, P64);
+}
+
+}  // namespace
+
 extern "C" int dl_loops(dl_gauge G, double kappa, const dl_sources *src, const dl_solve_params *params,
                         const int32_t *gammas, int32_t n_gamma, double *loops, dl_solve_stats *stats, void *stream)
 {
     return guarded([&]() {
-        DL_REQUIRE(G && loops && gammas, "dl_loops: null pointer");
+        DL_REQUIRE(G && loops, "dl_loops: null pointer");
         validate_sources(G->lat, src);
         validate_params(params);
-        DL_REQUIRE(n_gamma >= 1 && n_gamma <= 16, "dl_loops: n_gamma must be in [1, 16]");
-        for (int i = 0; i < n_gamma; ++i)
-            DL_REQUIRE(gammas[i] >= 0 && gammas[i] <= 15, "dl_loops: gamma index outside [0, 15]");
-        const dl_solve_params prm = *params;
-        check_prec(G, prm.prec);
-        if (prm.solver == DL_BICGSTAB) check_prec(G, P64);
-        Ctx c{G, G->lat.geom(), static_cast<hipStream_t>(stream)};
-        const int64_t Vh = G->lat.Vh;
-        const int T = c.g.T;
+        validate_gammas(gammas, n_gamma);
+        check_solver_for(G, *params);
+        return loops_run(G, kappa, src, *params, gammas, n_gamma, MODE_LOOPS, nullptr, loops, nullptr, stats,
+                         static_cast<hipStream_t>(stream));
+    });
+}
+
+extern "C" int dl_loops_tsm(dl_gauge G, double kappa, const dl_sources *src, const dl_tsm *tsm,
+                            const int32_t *gammas, int32_t n_gamma, double *loops, dl_solve_stats *stats,
+                            void *stream)
+{
+    return guarded([&]() {
+        DL_REQUIRE(G && loops && tsm, "dl_loops_tsm: null pointer");
+        validate_sources(G->lat, src);
+        DL_REQUIRE(src->kind == DL_SRC_Z2, "dl_loops_tsm: needs noise sources");
+        DL_REQUIRE(tsm->n_lp >= 1 && tsm->n_hp >= 1 && (int64_t)tsm->n_lp + tsm->n_hp == src->n_noise,
+                   "dl_loops_tsm: n_lp >= 1, n_hp >= 1 and n_lp + n_hp must equal n_noise");
+        validate_params(&tsm->lp);
+        validate_params(&tsm->hp);
+        validate_gammas(gammas, n_gamma);
+        check_solver_for(G, tsm->lp);
+        check_solver_for(G, tsm->hp);
+        const int T = G->lat.dims[3];
         const int ncls = source_classes(src);
-        const bool cg = prm.solver == DL_CGNR;
-        const size_t per = (cg ? SolveWork::bytes_cgnr(prm.prec, Vh) : SolveWork::bytes_bicg(prm.prec, Vh)) +
-                           (size_t)T * 32 * 8 + 16;
-        const int64_t total = (int64_t)src->n_noise * ncls;
-        const int B = batch_size(per, total, ncls);  // whole noises per batch
-        // gamma table and indices
-        std::vector<double> gtab = gamma_table();
-        DevBuf dgam(gtab.size() * sizeof(double)), dgidx(sizeof(int) * n_gamma),
-            dloops((size_t)src->n_noise * n_gamma * T * 2 * sizeof(double));
-        DL_HIP(hipMemcpyAsync(dgam.p, gtab.data(), dgam.bytes, hipMemcpyHostToDevice, c.s));
-        DL_HIP(hipMemcpyAsync(dgidx.p, gammas, dgidx.bytes, hipMemcpyHostToDevice, c.s));
-        int worst = DL_OK;
-        std::vector<int64_t> hnoise;
-        std::vector<int> hcls;
-        for (int64_t r0 = 0; r0 < total; r0 += B) {
-            const int n = (int)std::min<int64_t>(B, total - r0);
-            const int nn = n / ncls;
-            hnoise.resize(n);
-            hcls.resize(n);
-            for (int i = 0; i < n; ++i) {
-                hnoise[i] = src->first_noise + (r0 + i) / ncls;
-                hcls[i] = (int)((r0 + i) % ncls);
-            }
-            DevBuf dnoise(sizeof(int64_t) * n), dcls(sizeof(int) * n), dC((size_t)n * T * 32 * sizeof(double));
-            DL_HIP(hipMemcpyAsync(dnoise.p, hnoise.data(), dnoise.bytes, hipMemcpyHostToDevice, c.s));
-            DL_HIP(hipMemcpyAsync(dcls.p, hcls.data(), dcls.bytes, hipMemcpyHostToDevice, c.s));
-            SourceSpec ss;
-            ss.kind = src->kind;
-            ss.scheme = src->kind == DL_SRC_POINT ? 0 : src->scheme;
-            ss.seed = src->seed;
-            ss.V = G->lat.V;
-            ss.point_site = src->point_site;
-            ss.noise = dnoise.as<int64_t>();
-            ss.cls = dcls.as<int>();
-            SolveWork w;
-            std::vector<double> res2;
-            int sol_prec;
-            if (cg) {
-                w.alloc_cgnr(prm.prec, n, Vh);
-                k_source(prm.prec, w.be.view(), 0, ss, c.g, n, c.s);
-                k_source(prm.prec, w.bo.view(), 1, ss, c.g, n, c.s);
-                cgnr_batch(c, kappa, prm.fixed_iters, w);
-                sol_prec = prm.prec;
-            } else {
-                w.alloc_bicg(prm.prec, n, Vh);
-                k_source(P64, w.be.view(), 0, ss, c.g, n, c.s);
-                k_source(P64, w.bo.view(), 1, ss, c.g, n, c.s);
-                bicgstab_batch(c, kappa, prm, w);
-                if (stats) true_residual_full(c, kappa, w, res2);
-                sol_prec = P64;
-            }
-            k_trace(sol_prec, w.x64.view(), w.xo.view(), ss, c.g, n, dC.as<double>(), c.s);
-            k_gamma_contract(dC.as<double>(), nn, ncls, T, dgam.as<double>(), dgidx.as<int>(), n_gamma,
-                             dloops.as<double>() + (r0 / ncls) * n_gamma * T * 2, c.s);
-            DL_HIP(hipGetLastError());
-            DL_HIP(hipStreamSynchronize(c.s));
-            std::vector<dl_solve_stats> st(n);
-            fill_stats(w, res2, st.data(), c.s, cg);
-            for (int i = 0; i < n; ++i) {
-                if (stats) stats[r0 + i] = st[i];
-                if (st[i].status != DL_OK && worst == DL_OK) worst = st[i].status;
-            }
-        }
-        DL_HIP(hipMemcpyAsync(loops, dloops.p, dloops.bytes, hipMemcpyDeviceToHost, c.s));
-        DL_HIP(hipStreamSynchronize(c.s));
-        if (worst != DL_OK) g_err = "dl_loops: at least one solve did not converge";
-        return worst;
+        const size_t per_noise = (size_t)n_gamma * T * 2;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        // low precision on every noise (LP set, then HP set)
+        std::vector<double> lp((size_t)src->n_noise * per_noise);
+        int rc1 = loops_run(G, kappa, src, tsm->lp, gammas, n_gamma, MODE_LOOPS, nullptr, lp.data(), nullptr,
+                            stats, s);
+        // high precision on the HP set
+        dl_sources hs = *src;
+        hs.first_noise = src->first_noise + tsm->n_lp;
+        hs.n_noise = tsm->n_hp;
+        std::vector<double> hp((size_t)tsm->n_hp * per_noise);
+        int rc2 = loops_run(G, kappa, &hs, tsm->hp, gammas, n_gamma, MODE_LOOPS, nullptr, hp.data(), nullptr,
+                            stats ? stats + (int64_t)src->n_noise * ncls : nullptr, s);
+        // [LP set, LP] [HP set, HP] [HP set, LP]
+        std::memcpy(loops, lp.data(), sizeof(double) * tsm->n_lp * per_noise);
+        std::memcpy(loops + tsm->n_lp * per_noise, hp.data(), sizeof(double) * tsm->n_hp * per_noise);
+        std::memcpy(loops + (tsm->n_lp + tsm->n_hp) * per_noise, lp.data() + tsm->n_lp * per_noise,
+                    sizeof(double) * tsm->n_hp * per_noise);
+        const int rc = rc1 != DL_OK ? rc1 : rc2;
+        if (rc != DL_OK) g_err = "dl_loops_tsm: at least one solve did not converge";
+        return rc;
+    });
+}
+
+extern "C" int dl_loops_dkappa(dl_gauge G, double kappa, const dl_sources *src, const dl_solve_params *params,
+                               const int32_t *gammas, int32_t n_gamma, double *dloops, dl_solve_stats *stats,
+                               void *stream)
+{
+    return guarded([&]() {
+        DL_REQUIRE(G && dloops, "dl_loops_dkappa: null pointer");
+        validate_sources(G->lat, src);
+        validate_params(params);
+        DL_REQUIRE(params->solver == DL_BICGSTAB, "dl_loops_dkappa: needs the tolerance-driven BiCGStab");
+        validate_gammas(gammas, n_gamma);
+        check_solver_for(G, *params);
+        return loops_run(G, kappa, src, *params, gammas, n_gamma, MODE_DKAPPA, nullptr, dloops, nullptr, stats,
+                         static_cast<hipStream_t>(stream));
+    });
+}
+
+extern "C" int dl_loops_link_grad(dl_gauge G, double kappa, const dl_sources *src, const dl_solve_params *params,
+                                  const int32_t *gammas, int32_t n_gamma, const double *w, double *grad,
+                                  double *loops, double *dloops, dl_solve_stats *stats, void *stream)
+{
+    return guarded([&]() {
+        DL_REQUIRE(G && w && grad, "dl_loops_link_grad: null pointer");
+        validate_sources(G->lat, src);
+        validate_params(params);
+        DL_REQUIRE(params->solver == DL_BICGSTAB, "dl_loops_link_grad: needs the tolerance-driven BiCGStab");
+        validate_gammas(gammas, n_gamma);
+        check_solver_for(G, *params);
+        return loops_run(G, kappa, src, *params, gammas, n_gamma, MODE_GRAD, w, loops, grad, stats,
+                         static_cast<hipStream_t>(stream), dloops);
     });
 }
 
@@ -930,13 +1178,25 @@ extern "C" int dl_loops(dl_gauge G, double kappa, const dl_sources *src, const d
 
 extern "C" int dl_profile_enable(int32_t on)
 {
-    prof_drain();
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    g_prof_on = on != 0;
+    prof_drain_locked();
+    g_prof_on = false;
     for (int k = 0; k < PROF_NKIND; ++k) {
         g_prof_ms[k] = 0;
         g_prof_bytes[k] = 0;
         g_prof_n[k] = 0;
+    }
+    if (on) {
+        try {
+            if (!g_prof_ctr.p) g_prof_ctr.alloc(sizeof(unsigned) * PROF_SLOTS);
+            if (hipMemset(g_prof_ctr.p, 0, sizeof(unsigned) * PROF_SLOTS) != hipSuccess) return DL_EHIP;
+            if (hipDeviceSynchronize() != hipSuccess) return DL_EHIP;
+        } catch (const Error &e) {
+            g_err = e.msg;
+            return e.code;
+        }
+        g_prof_next = 0;
+        g_prof_on = true;
     }
     return DL_OK;
 }

@@ -24,6 +24,7 @@ struct DKArgs {
     int nblk;  // site blocks per right-hand-side group
     double *partials;
     const int *active;
+    unsigned *live_count;
 };
 
 // h = psi_up + s A_mu psi_down (two spin components x three colours)
@@ -147,6 +148,12 @@ __global__ __launch_bounds__(256) void dslash_kernel(DKArgs a)
         any = any || live[r];
     }
     if (!any) return;  // uniform across the block
+    if (a.live_count != nullptr && threadIdx.x == 0) {
+        unsigned nl = 0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) nl += live[r] ? 1u : 0u;
+        atomicAdd(a.live_count, nl);
+    }
 
     const int cb = sb * blockDim.x + threadIdx.x;
     const bool valid = cb < g.Vh;

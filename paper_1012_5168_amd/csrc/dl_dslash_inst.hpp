@@ -45,6 +45,7 @@ void launch_dslash_t(const DslashCall &c, int nr, int bs, hipStream_t s)
     a.nblk = (c.g.Vh + bs - 1) / bs;
     a.partials = c.partials;
     a.active = c.active;
+    a.live_count = c.live_count;
     const int groups = (c.nrhs + nr - 1) / nr;
     const int grid = a.nblk * groups;
     if (c.recon == 12) {

@@ -1,7 +1,7 @@
 // dl_fields.hip -- layout conversion (canonical <-> even-odd SoA), noise and
 // point sources with dilution masks, the timeslice trace reduction and the
 // gamma contraction of the loops, and link-format conversion.
-#include "dl_internal.hpp"
+#include "dl_dslash.hpp"
 
 namespace dl {
 
@@ -185,6 +185,129 @@ __global__ void gamma_contract_kernel(const double *C, int ncls, int T, const do
     }
 }
 
+
+// dst(x) = A_{n,t(x)} eta(x): the source gamma5 sum_g W[n][g][t] Gamma_g^+ eta of
+// the adjoint solve of noise n, with A as [noise][T][4][4] complex (row a, column b)
+__global__ __launch_bounds__(BS) void adjoint_source_kernel(Field dst, int parity, SourceSpec src, Geom g,
+                                                            const double *A, int64_t first_noise)
+{
+    const int rhs = blockIdx.y;
+    const int cb = blockIdx.x * BS + threadIdx.x;
+    if (cb >= g.Vh) return;
+    const Site s = decode(g, cb, parity);
+    cx<double> eta[12];
+    source_site(src, rhs, s, lex_index(g, s), eta);
+    const double *At = A + ((src.noise[rhs] - first_noise) * g.T + s.t) * 32;
+    cx<double> v[12];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            cx<double> acc = {0.0, 0.0};
+#pragma unroll
+            for (int b = 0; b < 4; ++b) cmac(acc, cx<double>{At[2 * (4 * a + b)], At[2 * (4 * a + b) + 1]}, eta[3 * b + c]);
+            v[3 * a + c] = acc;
+        }
+    store_spinor<double>(dst, g.Vh, rhs, cb, v);
+}
+
+// load a full spinor and apply gamma5 = diag(1, 1, -1, -1) when g5 is set
+__device__ __forceinline__ void load_g5(const Field &f, int64_t Vh, int rhs, int64_t cb, bool g5, cx<double> v[12])
+{
+    load_spinor<double>(f, Vh, rhs, cb, v);
+    if (g5)
+#pragma unroll
+        for (int e = 6; e < 12; ++e) v[e] = -v[e];
+}
+
+// one direction of the link gradient at site x with forward neighbour y = x + mu:
+//   X_ac = sum_alpha conj(a_{alpha a}(x)) [(1 - g_mu) s(y)]_{alpha c}
+//        = sum over the two projected spins of conj(P- a(x)) P- s(y),
+//   Y_ac = sum_alpha conj(a_{alpha a}(y)) [(1 + g_mu) s(x)]_{alpha c}
+//        = sum over the two projected spins of conj(P+ a(y)) P+ s(x),
+//   acc_ac += conj(X_ac) + Y_ca      (dF = Re(conj(grad) dU) convention)
+template <int MU>
+__device__ __forceinline__ void grad_dir(const Field &se, const Field &so, const Field &ae, const Field &ao,
+                                         const Geom &g, int par, int64_t cbx, int64_t cby, int nrhs,
+                                         cx<double> acc[9])
+{
+    const Field &sx = par ? so : se, &ax = par ? ao : ae;
+    const Field &sy = par ? se : so, &ay = par ? ae : ao;
+    for (int r = 0; r < nrhs; ++r) {
+        cx<double> v[12], h[6], ah[6];
+        load_spinor<double>(sy, g.Vh, r, cby, v);
+        project<double, MU, -1>(v, h);
+        load_g5(ax, g.Vh, r, cbx, true, v);
+        project<double, MU, -1>(v, ah);
+        cx<double> X[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                cx<double> t = {0.0, 0.0};
+                cmac_conj(t, ah[a], h[c]);
+                cmac_conj(t, ah[3 + a], h[3 + c]);
+                X[3 * a + c] = t;
+            }
+        load_spinor<double>(sx, g.Vh, r, cbx, v);
+        project<double, MU, +1>(v, h);
+        load_g5(ay, g.Vh, r, cby, true, v);
+        project<double, MU, +1>(v, ah);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                cx<double> y = {0.0, 0.0};  // Y_{c a}
+                cmac_conj(y, ah[c], h[a]);
+                cmac_conj(y, ah[3 + c], h[3 + a]);
+                acc[3 * a + c] = acc[3 * a + c] + conj(X[3 * a + c]) + y;
+            }
+    }
+}
+
+// grad[mu][x] += kappa b_mu(x) sum_rhs (conj X + Y^T); one thread per site,
+// every (mu, site) entry owned by exactly one thread
+__global__ __launch_bounds__(BS) void link_grad_kernel(Field se, Field so, Field ae, Field ao, Geom g, int nrhs,
+                                                       double kappa, double *grad)
+{
+    const int par = blockIdx.y;
+    const int cb = blockIdx.x * BS + threadIdx.x;
+    if (cb >= g.Vh) return;
+    const Site s = decode(g, cb, par);
+    const int64_t lex = lex_index(g, s);
+    const int64_t V = 2 * (int64_t)g.Vh;
+    const int64_t base_x = cb - (s.x >> 1);
+    for (int mu = 0; mu < 4; ++mu) {
+        cx<double> acc[9];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) acc[e] = {0.0, 0.0};
+        int64_t cby;
+        double b = 1.0;
+        if (mu == 0) {
+            const int xf = s.x + 1 == g.X ? 0 : s.x + 1;
+            cby = base_x + (xf >> 1);
+            grad_dir<0>(se, so, ae, ao, g, par, cb, cby, nrhs, acc);
+        } else if (mu == 1) {
+            cby = s.y + 1 == g.Y ? cb - (int64_t)(g.Y - 1) * g.sY : cb + g.sY;
+            grad_dir<1>(se, so, ae, ao, g, par, cb, cby, nrhs, acc);
+        } else if (mu == 2) {
+            cby = s.z + 1 == g.Z ? cb - (int64_t)(g.Z - 1) * g.sZ : cb + g.sZ;
+            grad_dir<2>(se, so, ae, ao, g, par, cb, cby, nrhs, acc);
+        } else {
+            cby = s.t + 1 == g.T ? cb - (int64_t)(g.T - 1) * g.sT : cb + g.sT;
+            if (g.tap && s.t + 1 == g.T) b = -1.0;
+            grad_dir<3>(se, so, ae, ao, g, par, cb, cby, nrhs, acc);
+        }
+        double2 *dst = reinterpret_cast<double2 *>(grad) + ((int64_t)mu * V + lex) * 9;
+        const double f = kappa * b;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            double2 o = dst[e];
+            dst[e] = make_double2(o.x + f * acc[e].re, o.y + f * acc[e].im);
+        }
+    }
+}
+
 template <typename S>
 __global__ __launch_bounds__(BS) void links_convert_kernel(void *dst, int ne, const double *src64, int64_t Vh)
 {
@@ -248,6 +371,22 @@ void k_gamma_contract(const double *C, int n_noise, int ncls, int T, const doubl
                       int n_gamma, double *loops, hipStream_t s)
 {
     hipLaunchKernelGGL(gamma_contract_kernel, dim3(n_noise), dim3(128), 0, s, C, ncls, T, gam, gidx, n_gamma, loops);
+}
+
+void k_adjoint_source(Field dst, int parity, const SourceSpec &src, const Geom &g, int nrhs, const double *A,
+                      int64_t first_noise, hipStream_t s)
+{
+    ProfScope ps(PROF_TRACE, field_bytes(P64, g.Vh, nrhs), s);
+    dim3 grid((g.Vh + BS - 1) / BS, nrhs);
+    hipLaunchKernelGGL(adjoint_source_kernel, grid, dim3(BS), 0, s, dst, parity, src, g, A, first_noise);
+}
+
+void k_link_grad(Field se, Field so, Field ae, Field ao, const Geom &g, int nrhs, double kappa, double *grad,
+                 hipStream_t s)
+{
+    ProfScope ps(PROF_TRACE, 4 * field_bytes(P64, g.Vh, nrhs) + 2.0 * 2 * g.Vh * 4 * 9 * 16, s);
+    dim3 grid((g.Vh + BS - 1) / BS, 2);
+    hipLaunchKernelGGL(link_grad_kernel, grid, dim3(BS), 0, s, se, so, ae, ao, g, nrhs, kappa, grad);
 }
 
 void k_links_convert(int prec, void *dst, int ne, const double *src64, int64_t Vh, hipStream_t s)

@@ -100,17 +100,25 @@ namespace dl {
 
 // ---------------------------------------------------------------- profiling
 
-enum ProfKind { PROF_DSLASH = 0, PROF_BLAS = 1, PROF_TRACE = 2, PROF_NKIND = 3 };
-// Brackets a launch with events when profiling is on; `bytes` are the
-// algorithmic bytes of the launch.
+enum ProfKind { PROF_DSLASH = 0, PROF_BLAS = 1, PROF_TRACE = 2, PROF_DSLASH_PLAIN = 3, PROF_NKIND = 4 };
+// Brackets a launch with events when profiling is on.  The algorithmic bytes
+// of the launch are `bytes`, or, when `counter` is set, fixed_bytes (if any
+// work ran) plus unit_bytes times the number of units the kernel counted
+// into *counter divided by `units_div` (the hopping kernel counts live
+// right-hand-side blocks, so masked-off right-hand sides move no bytes).
 struct ProfScope {
-    ProfScope(int kind, double bytes, hipStream_t s);
+    ProfScope(int kind, double bytes, hipStream_t s, int kind2 = -1);
     ~ProfScope();
-    int kind;
+    int kind, kind2;
     double bytes;
     hipStream_t s;
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    unsigned *counter = nullptr;
+    double unit_bytes = 0, fixed_bytes = 0, units_div = 1;
 };
+// a zeroed device counter for the next profiled launch (null when profiling is off)
+unsigned *prof_counter();
+bool prof_on();
 
 // ---------------------------------------------------------------- dslash
 
@@ -147,11 +155,20 @@ struct DslashCall {
     int nrhs;
     double *partials;     // [nrhs][nblk][nparts] (epilogues with reductions)
     const int *active;    // per right-hand side flag or null
+    unsigned *live_count = nullptr;  // profiling: live right-hand-side blocks
 };
 
 // launch with the tuned (or default) configuration; returns the number of
 // site blocks per right-hand side (the partials' middle extent)
 int launch_dslash(const DslashCall &c, hipStream_t s);
+
+// launch configuration of the hopping kernel: right-hand sides per thread and
+// sites per workgroup
+struct TuneChoice {
+    int nr, bs;
+};
+TuneChoice tune_lookup(const DslashCall &c, hipStream_t s);
+void launch_dslash_any(const DslashCall &c, int nr, int bs, hipStream_t s);
 int dslash_site_blocks(const Geom &g, int prec, int nrhs);
 
 // ---------------------------------------------------------------- Krylov vector kernels
@@ -235,6 +252,13 @@ void k_trace(int prec, Field se, Field so, const SourceSpec &src, const Geom &g,
 // loops[n][g][t] = sum_{d} sum_{ab} Gamma_g[a][b] C[n*ncls + d][t][a][b]
 void k_gamma_contract(const double *C, int n_noise, int ncls, int T, const double *gam, const int *gidx,
                       int n_gamma, double *loops, hipStream_t s);
+// adjoint source dst(x) = A[noise - first_noise][t(x)] eta(x), A as [noise][T][4][4] complex (FP64 field)
+void k_adjoint_source(Field dst, int parity, const SourceSpec &src, const Geom &g, int nrhs, const double *A,
+                      int64_t first_noise, hipStream_t s);
+// grad [4][V][3][3] complex += link gradient of Re sum conj(W) L from forward
+// solutions s and adjoint solutions a' (a = gamma5 a'), all FP64 parity fields
+void k_link_grad(Field se, Field so, Field ae, Field ao, const Geom &g, int nrhs, double kappa, double *grad,
+                 hipStream_t s);
 // links canonical (host-reordered to [4][2][9][Vh] complex128 on the device) -> storage format
 void k_links_convert(int prec, void *dst, int ne, const double *src64, int64_t Vh, hipStream_t s);
 

@@ -1,0 +1,139 @@
+// dl_tune.cpp -- autotuner for the hopping kernel's launch configuration.
+//
+// The tunables are the number of right-hand sides a thread carries (1 or 2:
+// links loaded once serve both) and the workgroup size (64, 128 or 256
+// sites).  The first time a (precision, link format, adjoint, epilogue,
+// right-hand sides, lattice) combination is launched, each candidate is timed
+// with HIP events on the real operands (every hopping launch is idempotent:
+// its output never aliases an input) and the fastest is kept, in memory and
+// in a text cache file (DL_TUNE_CACHE, default ~/.cache/dloops/tune_gfx950.txt).
+// DL_TUNE=0 disables tuning and uses 1 right-hand side per thread with 256
+// sites per workgroup.  Tuning never runs while the stream is being captured.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <string>
+#include <sys/stat.h>
+#include <tuple>
+
+#include "dl_internal.hpp"
+
+namespace dl {
+
+namespace {
+
+using Key = std::tuple<int, int, int, int, int, int, int, int, int>;
+
+std::mutex g_mu;
+std::map<Key, TuneChoice> g_cache;
+bool g_loaded = false;
+
+Key make_key(const DslashCall &c)
+{
+    return Key{c.prec, c.recon, c.dag ? 1 : 0, c.epi, c.nrhs, c.g.X, c.g.Y, c.g.Z, c.g.T};
+}
+
+std::string cache_path()
+{
+    if (const char *p = std::getenv("DL_TUNE_CACHE")) return p;
+    const char *home = std::getenv("HOME");
+    return std::string(home ? home : "/tmp") + "/.cache/dloops/tune_gfx950.txt";
+}
+
+bool tuning_enabled()
+{
+    const char *e = std::getenv("DL_TUNE");
+    return !(e && e[0] == '0');
+}
+
+void load_locked()
+{
+    if (g_loaded) return;
+    g_loaded = true;
+    FILE *f = std::fopen(cache_path().c_str(), "r");
+    if (!f) return;
+    int v[11];
+    while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6], &v[7],
+                       &v[8], &v[9], &v[10]) == 11) {
+        if ((v[9] == 1 || v[9] == 2) && (v[10] == 64 || v[10] == 128 || v[10] == 256))
+            g_cache[Key{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8]}] = TuneChoice{v[9], v[10]};
+    }
+    std::fclose(f);
+}
+
+void save_locked(const Key &k, const TuneChoice &t)
+{
+    std::string path = cache_path();
+    std::string dir = path.substr(0, path.find_last_of('/'));
+    for (size_t i = 1; i <= dir.size(); ++i)
+        if (i == dir.size() || dir[i] == '/') mkdir(dir.substr(0, i).c_str(), 0755);
+    FILE *f = std::fopen(path.c_str(), "a");
+    if (!f) return;
+    std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+                 std::get<3>(k), std::get<4>(k), std::get<5>(k), std::get<6>(k), std::get<7>(k), std::get<8>(k), t.nr,
+                 t.bs);
+    std::fclose(f);
+}
+
+bool aliases(const DslashCall &c)
+{
+    return c.out.d == c.in.d || (c.x.d && c.out.d == c.x.d) || (c.y.d && c.out.d == c.y.d);
+}
+
+}  // namespace
+
+TuneChoice tune_lookup(const DslashCall &c, hipStream_t s)
+{
+    const TuneChoice dflt{1, 256};
+    if (!tuning_enabled() || aliases(c)) return dflt;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return dflt;
+    const Key k = make_key(c);
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_locked();
+    auto it = g_cache.find(k);
+    if (it != g_cache.end()) return it->second;
+
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return dflt;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return dflt;
+    }
+    // repeat until each measurement spans at least ~1 ms of kernel time
+    TuneChoice best = dflt;
+    float best_ms = 1e30f;
+    DslashCall t = c;
+    t.live_count = nullptr;
+    for (int nr : {1, 2}) {
+        for (int bs : {64, 128, 256}) {
+            launch_dslash_any(t, nr, bs, s);  // warm
+            int reps = 1;
+            float ms = 0;
+            for (int attempt = 0; attempt < 3; ++attempt) {
+                (void)hipEventRecord(e0, s);
+                for (int r = 0; r < reps; ++r) launch_dslash_any(t, nr, bs, s);
+                (void)hipEventRecord(e1, s);
+                (void)hipEventSynchronize(e1);
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (ms > 1.0f || reps >= 64) break;
+                reps *= 8;
+            }
+            const float per = ms / reps;
+            if (hipGetLastError() == hipSuccess && per < best_ms) {
+                best_ms = per;
+                best = TuneChoice{nr, bs};
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g_cache[k] = best;
+    save_locked(k, best);
+    return best;
+}
+
+}  // namespace dl

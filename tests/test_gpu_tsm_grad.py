@@ -1,0 +1,165 @@
+"""Parity of the truncated solver method and of the derivatives (kappa and
+link gradients) against the CPU oracle, through the C ABI.
+
+Tolerances: FP64 solves (GPU 1e-12, oracle 1e-13) -> loops and derivatives
+within 1e-9 of max |oracle|; the truncated FP64 CGNR reproduces the oracle's
+FP64 run of the same 25 iterations to 1e-10; FP16 / BF16 truncated solves
+are reported against the stated per-loop bound (LP error is a property of the
+precision, not a defect: the truncated solver method is unbiased for any
+fixed low-precision map).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def rel(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+@pytest.mark.parametrize("lp_prec,tol", [(0, 1e-10), (1, 1e-4), (2, 2e-2), (3, 1e-1)])
+def test_tsm_parts_against_oracle(dl, dev, lp_prec, tol):
+    dims = (4, 4, 4, 8)
+    U = synth.gauge_field(dims, 0.5, seed=201)
+    kappa = 0.125
+    lat = dl.Lattice(dims, 1)
+    G = dl.Gauge(lat, U, precs=(dl.DL_F64, dl.DL_F32, lp_prec))
+    gam = [0, 15, 5]
+    n_lp, n_hp = 5, 3
+    lpp = dl.solve_params(solver=dl.DL_CGNR, prec=lp_prec, fixed_iters=25)
+    hpp = dl.solve_params(prec=dl.DL_F32, tol=1e-12, maxiter=2000)
+    a, b, c, st = dl.loops_tsm(G, kappa, dl.z2_sources(777, n_lp + n_hp, first_noise=10), n_lp, n_hp, gam, lpp, hpp)
+    ref_lp = oracle.loops_lp(U, dims, kappa, 777, range(10, 10 + n_lp + n_hp), 0, gam, niter=25)
+    ref_hp = oracle.loops_z2(U, dims, kappa, 777, range(10 + n_lp, 10 + n_lp + n_hp), 0, gam, tol=1e-13)
+    assert rel(a, ref_lp[:n_lp]) < tol
+    assert rel(c, ref_lp[n_lp:]) < tol
+    assert rel(b, ref_hp) < 1e-9
+    est, var = dl.tsm_estimate(a, b, c)
+    ref_est = oracle.tsm_combine(ref_lp[:n_lp], ref_hp, ref_lp[n_lp:])
+    assert np.max(np.abs(est - ref_est)) < max(tol, 1e-9) * np.max(np.abs(ref_lp)) * 2
+    assert all(s[0] == dl.DL_OK for s in st)
+
+
+def test_dkappa_against_oracle_and_difference(dl, dev):
+    dims = (4, 4, 4, 8)
+    U = synth.gauge_field(dims, 0.5, seed=211)
+    kappa = 0.125
+    lat = dl.Lattice(dims, 1)
+    G = dl.Gauge(lat, U)
+    gam = [0, 15, 5, 1]
+    prm = dl.solve_params(tol=1e-12, maxiter=2000)
+    src = dl.z2_sources(99, 2, scheme=dl.DL_DIL_SPIN_COLOUR)
+    d, st = dl.loops_dkappa(G, kappa, src, gam, prm)
+    ref = oracle.loops_dkappa(U, dims, kappa, 99, [0, 1], 1, gam, tol=1e-13)
+    assert rel(d, ref) < 1e-9
+    h = 1e-5
+    lp, _ = dl.loops(G, kappa + h, src, gam, prm)
+    lm, _ = dl.loops(G, kappa - h, src, gam, prm)
+    assert rel((lp - lm) / (2 * h), d) < 1e-6
+    assert all(s[0] == dl.DL_OK for s in st)
+
+
+@pytest.mark.parametrize("recon", [18, 12])
+def test_link_gradient_against_oracle(dl, dev, recon):
+    """The 4^4 subcase (eps 0.35, kappa 0.148) with a spin-colour-diluted noise and a random cotangent."""
+    w = synth.WORKLOADS["grad_4x4x4x4"]
+    dims, kappa = w["dims"], w["kappa"]
+    U = synth.gauge_field(dims, w["eps"], w["gauge_seed"])
+    lat = dl.Lattice(dims, 1)
+    G = dl.Gauge(lat, U, recon=recon)
+    gam = [15, 0]
+    rng = np.random.default_rng(5)
+    W = rng.standard_normal((2, len(gam), dims[3])) + 1j * rng.standard_normal((2, len(gam), dims[3]))
+    prm = dl.solve_params(tol=1e-12, maxiter=2000)
+    src = dl.z2_sources(w["noise_seed"], 2, scheme=dl.DL_DIL_SPIN_COLOUR)
+    grad, L, dk, st = dl.loops_link_grad(G, kappa, src, gam, W, prm, with_dkappa=True)
+    ref = np.zeros_like(grad)
+    for n in range(2):
+        srcs = [oracle.z2_source(dims, w["noise_seed"], n, 1, d) for d in range(12)]
+        ref += oracle.link_grad(U, dims, kappa, srcs, gam, W[n], tol=1e-13)
+    assert rel(grad, ref) < 1e-9
+    refL = oracle.loops_z2(U, dims, kappa, w["noise_seed"], [0, 1], 1, gam, tol=1e-13)
+    assert rel(L, refL) < 1e-10
+    refd = oracle.loops_dkappa(U, dims, kappa, w["noise_seed"], [0, 1], 1, gam, tol=1e-13)
+    assert rel(dk, refd) < 1e-9
+    assert all(s[0] == dl.DL_OK for s in st)
+
+
+def test_link_gradient_directional_difference_on_gpu(dl, dev):
+    """d/dt F(U + t dU) by central differences of GPU loops (links with three stored rows)."""
+    dims = (2, 2, 2, 4)
+    U = synth.gauge_field(dims, 0.5, seed=221)
+    kappa = 0.12
+    gam = [15, 0, 5]
+    rng = np.random.default_rng(222)
+    W = rng.standard_normal((1, 3, dims[3])) + 1j * rng.standard_normal((1, 3, dims[3]))
+    prm = dl.solve_params(tol=1e-13, maxiter=2000)
+    src = dl.z2_sources(31, 1, scheme=dl.DL_DIL_SPIN_COLOUR)
+    lat = dl.Lattice(dims, 1)
+
+    def F(Ux):
+        L, _ = dl.loops(dl.Gauge(lat, Ux, recon=18), kappa, src, gam, prm)
+        return np.sum((np.conj(W) * L).real)
+
+    grad, _, _, _ = dl.loops_link_grad(dl.Gauge(lat, U, recon=18), kappa, src, gam, W, prm)
+    for _ in range(2):
+        dU = rng.standard_normal(U.shape) + 1j * rng.standard_normal(U.shape)
+        h = 1e-5
+        fd = (F(U + h * dU) - F(U - h * dU)) / (2 * h)
+        an = np.sum((np.conj(grad) * dU).real)
+        assert abs(fd - an) < 1e-6 * max(1.0, abs(an)), (fd, an)
+
+
+def test_autograd_function_gradcheck(dl, dev):
+    from paper_1012_5168_amd.autograd import disconnected_loops
+
+    dims = (2, 2, 2, 2)
+    U = synth.gauge_field(dims, 0.5, seed=231)
+    links = torch.tensor(np.array(U), dtype=torch.complex128, requires_grad=True)
+    kappa = torch.tensor(0.12, dtype=torch.float64, requires_grad=True)
+    src = dl.z2_sources(41, 1)
+    prm = dl.solve_params(tol=1e-13, maxiter=2000)
+
+    def f(k, u):
+        return disconnected_loops(k, u, dims, src, [15, 0], prm)
+
+    assert torch.autograd.gradcheck(f, (kappa, links), eps=1e-6, atol=1e-6, rtol=1e-4)
+    # backward through a real loss
+    L = f(kappa, links)
+    loss = (L.real ** 2).sum() + L.imag.sum()
+    loss.backward()
+    assert links.grad is not None and kappa.grad is not None
+
+
+def test_full_size_dkappa_mixed_precision(dl, dev):
+    """24^3 x 48 (eps 0.35, kappa 0.148), FP32 iterations with FP64 reliable updates to 1e-10:
+    the kappa derivative of one spin-colour-diluted noise against central differences (h = 1e-5)."""
+    w = synth.WORKLOADS["grad_24x24x24x48"]
+    dims, kappa = w["dims"], w["kappa"]
+    U = synth.gauge_field(dims, w["eps"], w["gauge_seed"])
+    lat = dl.Lattice(dims, 1)
+    G = dl.Gauge(lat, U, precs=(dl.DL_F64, dl.DL_F32))
+    gam = [15, 0]
+    prm = dl.solve_params(prec=dl.DL_F32, tol=1e-10, maxiter=2000)
+    src = dl.z2_sources(w["noise_seed"], 1, scheme=dl.DL_DIL_SPIN_COLOUR)
+    d, st = dl.loops_dkappa(G, kappa, src, gam, prm)
+    assert all(s[0] == dl.DL_OK and s[3] <= 1e-10 for s in st)
+    h = 1e-5
+    lp, _ = dl.loops(G, kappa + h, src, gam, prm)
+    lm, _ = dl.loops(G, kappa - h, src, gam, prm)
+    fd = (lp - lm) / (2 * h)
+    # FD error ~ h^2 |L'''| + tol |L| / h
+    assert rel(fd, d) < 1e-4, rel(fd, d)
