@@ -147,6 +147,8 @@ typedef struct {
     double delta;        /* reliable-update trigger: |r| < delta * max |r| since the last update
                             (0 -> 0.1) */
     int32_t poll;        /* iterations between host convergence checks (0 -> automatic) */
+    int32_t use_graph;   /* 1: capture `poll` BiCGStab iterations once as a hipGraph and replay it
+                            (the first chunk runs eagerly and tunes the launch shapes) */
 } dl_solve_params;
 
 /* Per right-hand side results of a solve. */
@@ -242,6 +244,20 @@ int dl_loops_dkappa(dl_gauge g, double kappa, const dl_sources *src, const dl_so
 int dl_loops_link_grad(dl_gauge g, double kappa, const dl_sources *src, const dl_solve_params *params,
                        const int32_t *gammas, int32_t n_gamma, const double *w, double *grad, double *loops,
                        double *dloops, dl_solve_stats *stats, void *stream);
+
+/*
+ * Loop estimates on up to 4 lattices of different shapes at once (each with
+ * its own gauge field, kappa and sources; one solver parameter set): every
+ * solver step is one launch over all lattices' right-hand sides, with
+ * params->use_graph replaying the captured iteration chunks.  Results per
+ * lattice exactly as dl_loops: loops[l] host [n_noise_l][n_gamma][T_l][2],
+ * stats[l] host [n_noise_l * classes_l] (stats or stats[l] may be NULL).
+ * Tolerance-driven BiCGStab only.  Errors: DL_EINVAL (n_lat outside [1, 4],
+ * null pointers, invalid sources or parameters).
+ */
+int dl_batch_loops(int32_t n_lat, const dl_gauge *gauges, const double *kappas, const dl_sources *srcs,
+                   const dl_solve_params *params, const int32_t *gammas, int32_t n_gamma, double *const *loops,
+                   dl_solve_stats *const *stats, void *stream);
 
 /* Number of right-hand sides (solves) a dl_sources description expands to, or < 0 if invalid. */
 int64_t dl_sources_count(dl_lattice lat, const dl_sources *src);

@@ -54,6 +54,7 @@ class dl_solve_params(ctypes.Structure):
         ("fixed_iters", ctypes.c_int32),
         ("delta", ctypes.c_double),
         ("poll", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32),
     ]
 
 
@@ -109,6 +110,8 @@ _SIGNATURES = {
     "dl_loops_link_grad": (ctypes.c_int, [_P, ctypes.c_double, ctypes.POINTER(dl_sources),
                                           ctypes.POINTER(dl_solve_params), _P, ctypes.c_int32, _P, _P, _P, _P,
                                           ctypes.POINTER(dl_solve_stats), _P]),
+    "dl_batch_loops": (ctypes.c_int, [ctypes.c_int32, _P, _P, _P, ctypes.POINTER(dl_solve_params), _P,
+                                      ctypes.c_int32, _P, _P, _P]),
     "dl_sources_count": (ctypes.c_int64, [_P, ctypes.POINTER(dl_sources)]),
     "dl_sources_fill": (ctypes.c_int, [_P, ctypes.POINTER(dl_sources), ctypes.c_int64, ctypes.c_int64, _P, _P]),
     "dl_profile_enable": (ctypes.c_int, [ctypes.c_int32]),
@@ -242,6 +245,20 @@ def dl_loops_link_grad(gauge, kappa, sources, params, gammas, w: np.ndarray, gra
     return rc
 
 
+def dl_batch_loops(gauges, kappas, sources, params, gammas, loops_out, stats=None, stream=None):
+    n = len(gauges)
+    gh = (_P * n)(*[g for g in gauges])
+    ks = (ctypes.c_double * n)(*[float(k) for k in kappas])
+    ss = (dl_sources * n)(*sources)
+    g = np.ascontiguousarray(np.asarray(gammas, dtype=np.int32))
+    lp = (_P * n)(*[a.ctypes.data_as(_P) for a in loops_out])
+    sp = None if stats is None else (_P * n)(*[ctypes.cast(x, _P) for x in stats])
+    rc = load().dl_batch_loops(n, gh, ks, ss, ctypes.byref(params), g.ctypes.data_as(_P), len(g), lp, sp,
+                               _stream(stream))
+    _check(rc, allow=(DL_ENOCONV,))
+    return rc
+
+
 def dl_sources_count(lat, sources) -> int:
     n = load().dl_sources_count(lat, ctypes.byref(sources))
     if n < 0:
@@ -266,8 +283,10 @@ def dl_profile_read(kind: int):
 # ------------------------------------------------------------------ handles and shorthands
 
 
-def solve_params(solver=DL_BICGSTAB, prec=DL_F64, tol=1e-10, maxiter=1000, fixed_iters=0, delta=0.0, poll=0):
-    return dl_solve_params(int(solver), int(prec), float(tol), int(maxiter), int(fixed_iters), float(delta), int(poll))
+def solve_params(solver=DL_BICGSTAB, prec=DL_F64, tol=1e-10, maxiter=1000, fixed_iters=0, delta=0.0, poll=0,
+                 use_graph=False):
+    return dl_solve_params(int(solver), int(prec), float(tol), int(maxiter), int(fixed_iters), float(delta), int(poll),
+                           1 if use_graph else 0)
 
 
 def z2_sources(seed, n_noise, first_noise=0, scheme=0):
@@ -401,3 +420,16 @@ def loops_link_grad(gauge: Gauge, kappa: float, sources: dl_sources, gammas, w, 
     dl_loops_link_grad(gauge.h, kappa, sources, params, gammas, wb, grad, loops, dk, st, stream)
     z = lambda a: None if a is None else a[..., 0] + 1j * a[..., 1]  # noqa: E731
     return z(grad), z(loops), z(dk), _stats_list(st)
+
+
+def batch_loops(gauges, kappas, sources, gammas, params=None, stream=None):
+    """Loop estimates on several lattices in one batched solve; returns lists of per-lattice
+    complex [n_noise][n_gamma][T] loops and stats."""
+    params = params or solve_params()
+    outs, stats = [], []
+    for G, src in zip(gauges, sources):
+        T = G.lattice.dims[3]
+        outs.append(np.zeros((int(src.n_noise), len(gammas), T, 2), dtype=np.float64))
+        stats.append((dl_solve_stats * dl_sources_count(G.lattice.h, src))())
+    dl_batch_loops([G.h for G in gauges], kappas, sources, params, gammas, outs, stats, stream)
+    return [o[..., 0] + 1j * o[..., 1] for o in outs], [_stats_list(s) for s in stats]

@@ -90,21 +90,30 @@ Field HalfField::view_rhs(int64_t r) const
 
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
+struct ProfSlot {
+    int slot;
+    double unit_bytes, fixed_bytes, units_div;
+};
 struct ProfRec {
     int kind, kind2;
     double bytes;
     hipEvent_t e0, e1;
-    int slot;  // counter slot or -1
-    double unit_bytes, fixed_bytes, units_div;
+    std::vector<ProfSlot> slots;
 };
 static std::vector<ProfRec> g_prof_pending;
 static double g_prof_ms[PROF_NKIND], g_prof_bytes[PROF_NKIND];
 static int64_t g_prof_n[PROF_NKIND];
-static DevBuf g_prof_ctr;  // device counters, one per profiled hopping launch
+static DevBuf g_prof_ctr;  // device counters, one per profiled hopping launch and lattice
 static int g_prof_next = 0;
 static const int PROF_SLOTS = 1 << 16;
 
 static void prof_drain_locked();
+
+static bool capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+}
 
 bool prof_on() { return g_prof_on; }
 
@@ -120,7 +129,7 @@ unsigned *prof_counter()
 ProfScope::ProfScope(int kind_, double bytes_, hipStream_t s_, int kind2_)
     : kind(kind_), kind2(kind2_), bytes(bytes_), s(s_)
 {
-    if (!g_prof_on) return;
+    if (!g_prof_on || capturing(s)) return;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         e0 = e1 = nullptr;
         return;
@@ -133,8 +142,11 @@ ProfScope::~ProfScope()
     if (!e0) return;
     (void)hipEventRecord(e1, s);
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    int slot = counter ? (int)(counter - g_prof_ctr.as<unsigned>()) : -1;
-    g_prof_pending.push_back({kind, kind2, bytes, e0, e1, slot, unit_bytes, fixed_bytes, units_div});
+    ProfRec r{kind, kind2, bytes, e0, e1, {}};
+    for (const ProfPart &p : parts)
+        if (p.counter)
+            r.slots.push_back({(int)(p.counter - g_prof_ctr.as<unsigned>()), p.unit_bytes, p.fixed_bytes, p.units_div});
+    g_prof_pending.push_back(r);
 }
 
 static void prof_drain_locked()
@@ -149,9 +161,12 @@ static void prof_drain_locked()
         float ms = 0;
         if (hipEventSynchronize(r.e1) == hipSuccess && hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) {
             double by = r.bytes;
-            if (r.slot >= 0 && r.slot < (int)ctr.size()) {
-                const double units = ctr[r.slot];
-                by = (units > 0 ? r.fixed_bytes : 0.0) + r.unit_bytes * units / r.units_div;
+            if (!r.slots.empty()) {
+                by = 0;
+                for (const ProfSlot &ps : r.slots) {
+                    const double units = (ps.slot >= 0 && ps.slot < (int)ctr.size()) ? ctr[ps.slot] : 0.0;
+                    by += (units > 0 ? ps.fixed_bytes : 0.0) + ps.unit_bytes * units / ps.units_div;
+                }
             }
             for (int k : {r.kind, r.kind2}) {
                 if (k < 0) continue;
@@ -182,7 +197,7 @@ static void prof_drain()
 int dslash_site_blocks(const Geom &g, int /*prec*/, int /*nrhs*/) { return (g.Vh + 63) / 64; }
 
 template <typename S>
-void launch_dslash_t(const DslashCall &c, int nr, int bs, hipStream_t s);
+void launch_dslash_t(const DslashCall *c, int nseg, int nr, int bs, int persistent, hipStream_t s);
 
 // algorithmic bytes of one launch: every operand moved once.  Per live
 // right-hand side: the input half spinor, the output and the epilogue
@@ -198,35 +213,39 @@ static void dslash_bytes(const DslashCall &c, double &per_rhs, double &links)
     per_rhs = nfield * field;
 }
 
-void launch_dslash_any(const DslashCall &c, int nr, int bs, hipStream_t s)
+void launch_dslash_any(const std::vector<DslashCall> &c, int nr, int bs, int persistent, hipStream_t s)
 {
-    switch (c.prec) {
-    case P64: launch_dslash_t<double>(c, nr, bs, s); break;
-    case P32: launch_dslash_t<float>(c, nr, bs, s); break;
-    case P16: launch_dslash_t<__half>(c, nr, bs, s); break;
-    default: launch_dslash_t<__hip_bfloat16>(c, nr, bs, s); break;
+    switch (c[0].prec) {
+    case P64: launch_dslash_t<double>(c.data(), (int)c.size(), nr, bs, persistent, s); break;
+    case P32: launch_dslash_t<float>(c.data(), (int)c.size(), nr, bs, persistent, s); break;
+    case P16: launch_dslash_t<__half>(c.data(), (int)c.size(), nr, bs, persistent, s); break;
+    default: launch_dslash_t<__hip_bfloat16>(c.data(), (int)c.size(), nr, bs, persistent, s); break;
     }
 }
 
-int launch_dslash(const DslashCall &c0, hipStream_t s)
+std::vector<int> launch_dslash_batch(const std::vector<DslashCall> &c0, hipStream_t s)
 {
+    if (c0.empty() || c0.size() > (size_t)MAXSEG) throw Error{DL_EINVAL, "internal: hopping batch size out of range"};
     const TuneChoice t = tune_lookup(c0, s);
-    DslashCall c = c0;
-    double per_rhs, links;
-    dslash_bytes(c, per_rhs, links);
-    const int nblk = (c.g.Vh + t.bs - 1) / t.bs;
-    c.live_count = prof_counter();
-    {
-        ProfScope ps(PROF_DSLASH, per_rhs * c.nrhs + links, s, (c.epi == EPI_PLAIN && !c.dag) ? PROF_DSLASH_PLAIN : -1);
-        ps.counter = c.live_count;
-        ps.unit_bytes = per_rhs;
-        ps.fixed_bytes = links;
-        ps.units_div = nblk;
-        launch_dslash_any(c, t.nr, t.bs, s);
+    std::vector<DslashCall> c = c0;
+    std::vector<int> nblk(c.size());
+    double nominal = 0;
+    const bool counted = prof_on() && !capturing(s);
+    ProfScope ps(PROF_DSLASH, 0.0, s, (c[0].epi == EPI_PLAIN && !c[0].dag) ? PROF_DSLASH_PLAIN : -1);
+    for (size_t k = 0; k < c.size(); ++k) {
+        double per_rhs, links;
+        dslash_bytes(c[k], per_rhs, links);
+        nblk[k] = (c[k].g.Vh + t.bs - 1) / t.bs;
+        nominal += per_rhs * c[k].nrhs + links;
+        c[k].live_count = counted ? prof_counter() : nullptr;
+        ps.parts.push_back({c[k].live_count, per_rhs, links, (double)nblk[k]});
     }
+    ps.bytes = nominal;
+    launch_dslash_any(c, t.nr, t.bs, t.persistent, s);
     return nblk;
 }
 
+int launch_dslash(const DslashCall &c, hipStream_t s) { return launch_dslash_batch({c}, s)[0]; }
 
 }  // namespace dl
 
@@ -455,7 +474,7 @@ extern "C" int dl_apply(dl_gauge G, double kappa, int32_t op, int32_t prec, cons
             launch_dslash(dcall(c, prec, 0, dag, EPI_XPAY, tmp.view(), oe.view(), ie.view(), NOF, -kappa * kappa, n,
                                 nullptr, nullptr),
                           c.s);
-            k_zero(prec, oo.view(), Vh, n, nullptr, c.s);
+            vec_launch(V_ZERO, prec, {VSeg{{oo.view(), NOF, NOF, NOF, NOF}, nullptr, nullptr, Vh, n, nullptr}}, c.s);
             break;
         }
         k_unpack(prec, oe.view(), 0, static_cast<double *>(out), c.g, n, c.s);
@@ -542,6 +561,137 @@ struct SolveWork {
 
 int parse_poll(const dl_solve_params &prm) { return prm.poll > 0 ? prm.poll : 4; }
 
+// ---- single-segment shorthands
+
+VSeg vs(std::initializer_list<Field> f, int64_t Vh, int n, const int *mask = nullptr, double *parts = nullptr,
+        const KState *st = nullptr)
+{
+    VSeg a;
+    int k = 0;
+    for (const Field &x : f) a.f[k++] = x;
+    for (; k < 5; ++k) a.f[k] = NOF;
+    a.st = st;
+    a.mask = mask;
+    a.Vh = Vh;
+    a.nrhs = n;
+    a.parts = parts;
+    return a;
+}
+
+void k_zero(int prec, Field f, int64_t Vh, int n, const int *mask, hipStream_t s)
+{
+    vec_launch(V_ZERO, prec, {vs({f}, Vh, n, mask)}, s);
+}
+
+void k_copy(int prec_dst, Field dst, int prec_src, Field src, int64_t Vh, int n, const int *mask, hipStream_t s)
+{
+    copy_launch(prec_dst, prec_src, {vs({dst, src}, Vh, n, mask)}, s);
+}
+
+// ---- batched solves: one problem per lattice, every step one launch over all of them
+
+struct Prob {
+    Ctx c;
+    double kappa;
+    SolveWork *w;
+    int64_t Vh() const { return c.g.Vh; }
+    int nb() const { return blas_blocks(c.g.Vh); }
+};
+
+template <typename F>
+std::vector<VSeg> VS(const std::vector<Prob> &P, F f)
+{
+    std::vector<VSeg> v;
+    for (const Prob &p : P) v.push_back(f(p));
+    return v;
+}
+template <typename F>
+std::vector<DslashCall> DS(const std::vector<Prob> &P, F f)
+{
+    std::vector<DslashCall> v;
+    for (const Prob &p : P) v.push_back(f(p));
+    return v;
+}
+// scalar segments with the partials' block count per problem
+std::vector<SSeg> SS(const std::vector<Prob> &P, const std::vector<int> &nblk, bool second_parts, const int *(*mask)(
+                                                                                                       const Prob &))
+{
+    std::vector<SSeg> v;
+    for (size_t k = 0; k < P.size(); ++k) {
+        SolveWork &w = *P[k].w;
+        SSeg a;
+        a.st = w.st.as<KState>();
+        a.act = w.act.as<int>();
+        a.upd = w.upd.as<int>();
+        a.restart = w.restart.as<int>();
+        a.mask = mask ? mask(P[k]) : nullptr;
+        a.parts = w.parts.as<double>();
+        a.parts2 = second_parts ? w.parts2.as<double>() : nullptr;
+        a.nblk = nblk[k];
+        a.nrhs = w.n;
+        v.push_back(a);
+    }
+    return v;
+}
+std::vector<int> blas_nb(const std::vector<Prob> &P)
+{
+    std::vector<int> v;
+    for (const Prob &p : P) v.push_back(p.nb());
+    return v;
+}
+const int *mask_restart(const Prob &p) { return p.w->restart.as<int>(); }
+
+// the launches of one BiCGStab iteration over all problems
+void bicg_iteration(const std::vector<Prob> &P, int prec, bool mixed, hipStream_t s)
+{
+    auto act = [](const Prob &p) { return p.w->act.as<int>(); };
+    vec_launch(V_BICG_P, prec, VS(P, [&](const Prob &p) {
+                   return vs({p.w->p.view(), p.w->r.view(), p.w->v.view()}, p.Vh(), p.w->n, act(p), nullptr,
+                             p.w->st.as<KState>());
+               }),
+               s);
+    launch_dslash_batch(DS(P, [&](const Prob &p) {
+                            return dcall(p.c, prec, 1, false, EPI_PLAIN, p.w->p.view(), p.w->tmpo.view(), NOF, NOF,
+                                         1.0, p.w->n, nullptr, act(p));
+                        }),
+                        s);
+    std::vector<int> nbd = launch_dslash_batch(DS(P, [&](const Prob &p) {
+                                                   return dcall(p.c, prec, 0, false, EPI_XPAY_DOT, p.w->tmpo.view(),
+                                                                p.w->v.view(), p.w->p.view(), p.w->rh.view(),
+                                                                -p.kappa * p.kappa, p.w->n, p.w->parts.as<double>(),
+                                                                act(p));
+                                               }),
+                                               s);
+    scalar_launch(S_BICG_ALPHA, SS(P, nbd, false, nullptr), SParams{}, s);
+    vec_launch(V_BICG_S, prec, VS(P, [&](const Prob &p) {
+                   return vs({p.w->r.view(), p.w->v.view()}, p.Vh(), p.w->n, act(p), nullptr, p.w->st.as<KState>());
+               }),
+               s);
+    launch_dslash_batch(DS(P, [&](const Prob &p) {
+                            return dcall(p.c, prec, 1, false, EPI_PLAIN, p.w->r.view(), p.w->tmpo.view(), NOF, NOF,
+                                         1.0, p.w->n, nullptr, act(p));
+                        }),
+                        s);
+    nbd = launch_dslash_batch(DS(P, [&](const Prob &p) {
+                                  return dcall(p.c, prec, 0, false, EPI_XPAY_TS, p.w->tmpo.view(), p.w->t.view(),
+                                               p.w->r.view(), NOF, -p.kappa * p.kappa, p.w->n, p.w->parts.as<double>(),
+                                               act(p));
+                              }),
+                              s);
+    scalar_launch(S_BICG_OMEGA, SS(P, nbd, false, nullptr), SParams{}, s);
+    vec_launch(V_BICG_XR, prec, VS(P, [&](const Prob &p) {
+                   Field xit = mixed ? p.w->xlo.view() : p.w->x64.view();
+                   return vs({xit, p.w->r.view(), p.w->p.view(), p.w->t.view(), p.w->rh.view()}, p.Vh(), p.w->n,
+                             act(p), p.w->parts.as<double>(), p.w->st.as<KState>());
+               }),
+               s);
+    SParams sp;
+    sp.np = 3;
+    sp.first = 0;
+    sp.mixed = mixed ? 1 : 0;
+    scalar_launch(S_BICG_RHO, SS(P, blas_nb(P), false, nullptr), sp, s);
+}
+
 int count_host(const DevBuf &flags, int n, hipStream_t s, std::vector<int> &h)
 {
     h.resize(n);
@@ -552,62 +702,118 @@ int count_host(const DevBuf &flags, int n, hipStream_t s, std::vector<int> &h)
     return c;
 }
 
-// BiCGStab on the even-site Schur system for w.n right-hand sides whose
-// sources are in w.be / w.bo (FP64).  Leaves x_e in w.x64 and x_o in w.xo
-// and the per right-hand side state in w.st.  Iterated vectors in w.prec;
-// below FP64 the iterate is folded into the FP64 x and the residual
-// recomputed in FP64 whenever |r| drops by delta since the last update.
-void bicgstab_batch(const Ctx &c, double kappa, const dl_solve_params &prm, SolveWork &w)
+int count_all(const std::vector<Prob> &P, bool upd, hipStream_t s)
 {
-    const int n = w.n, P = w.prec;
-    const bool mixed = P != P64;
-    const int64_t Vh = c.g.Vh;
-    const int nb = blas_blocks(Vh);
-    KState *st = w.st.as<KState>();
-    int *act = w.act.as<int>(), *upd = w.upd.as<int>(), *rst = w.restart.as<int>();
-    double *parts = w.parts.as<double>(), *parts2 = w.parts2.as<double>();
-    const double k2 = kappa * kappa;
+    std::vector<int> h;
+    int c = 0;
+    for (const Prob &p : P) c += count_host(upd ? p.w->upd : p.w->act, p.w->n, s, h);
+    return c;
+}
+
+// A stream that graph capture may use: the caller's stream unless it is the
+// legacy default stream, else a library stream ordered after it.
+struct CaptureStream {
+    hipStream_t user, s;
+    hipEvent_t ev = nullptr;
+    explicit CaptureStream(hipStream_t u) : user(u), s(u)
+    {
+        if (u != nullptr) return;
+        static hipStream_t own = nullptr;
+        static std::mutex mu;
+        std::lock_guard<std::mutex> lk(mu);
+        if (!own) DL_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+        s = own;
+        DL_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        DL_HIP(hipEventRecord(ev, user));
+        DL_HIP(hipStreamWaitEvent(s, ev, 0));
+    }
+    void join()
+    {
+        if (s == user) return;
+        DL_HIP(hipEventRecord(ev, s));
+        DL_HIP(hipStreamWaitEvent(user, ev, 0));
+    }
+    ~CaptureStream()
+    {
+        if (ev) (void)hipEventDestroy(ev);
+    }
+};
+
+// BiCGStab on the even-site Schur systems of every problem (sources in w.be /
+// w.bo, FP64).  Leaves x_e in w.x64, x_o in w.xo and the per right-hand side
+// state in w.st.  Iterated vectors in w.prec; below FP64 the iterate is folded
+// into the FP64 x and the residual recomputed in FP64 whenever |r| drops by
+// delta since the last update (at the poll points).  With use_graph each chunk
+// of `poll` iterations after the first is replayed from a captured hipGraph.
+void bicgstab_multi(const std::vector<Prob> &P0, const dl_solve_params &prm, hipStream_t user_stream)
+{
+    std::unique_ptr<CaptureStream> cst;
+    if (prm.use_graph) cst.reset(new CaptureStream(user_stream));
+    const hipStream_t s = cst ? cst->s : user_stream;
+    std::vector<Prob> P = P0;
+    for (Prob &p : P) p.c.s = s;
+    const int prec = P[0].w->prec;
+    const bool mixed = prec != P64;
     const double delta = mixed ? (prm.delta > 0 ? prm.delta : 0.1) : 0.0;
-    Field xit = mixed ? w.xlo.view() : w.x64.view();
+    auto upd = [](const Prob &p) { return (const int *)p.w->upd.as<int>(); };
 
     // |b|^2 over both parities; bhat = b_e + kappa D_eo b_o
-    k_norm2_parts(P64, w.be.view(), Vh, n, nullptr, parts, c.s);
-    k_norm2_parts(P64, w.bo.view(), Vh, n, nullptr, parts2, c.s);
-    k_bicg_init(st, act, upd, n, parts, parts2, nb, prm.tol * prm.tol, delta * delta, prm.maxiter, c.s);
-    launch_dslash(dcall(c, P64, 0, false, EPI_XPAY, w.bo.view(), w.bhat.view(), w.be.view(), NOF, kappa, n, nullptr,
-                        nullptr),
-                  c.s);
-    k_zero(P64, w.x64.view(), Vh, n, nullptr, c.s);
-    if (mixed) k_zero(P, w.xlo.view(), Vh, n, nullptr, c.s);
-    k_copy(P, w.r.view(), P64, w.bhat.view(), Vh, n, nullptr, c.s);
-    k_copy(P, w.rh.view(), P, w.r.view(), Vh, n, nullptr, c.s);
-    k_zero(P, w.p.view(), Vh, n, nullptr, c.s);
-    k_zero(P, w.v.view(), Vh, n, nullptr, c.s);
-    k_dot_parts(P, w.rh.view(), w.r.view(), Vh, n, nullptr, parts, c.s);
-    k_bicg_rho(st, act, upd, nullptr, n, parts, nb, 2, 1, mixed, c.s);
+    vec_launch(V_NORM2, P64, VS(P, [&](const Prob &p) {
+                   return vs({p.w->be.view()}, p.Vh(), p.w->n, nullptr, p.w->parts.as<double>());
+               }),
+               s);
+    vec_launch(V_NORM2, P64, VS(P, [&](const Prob &p) {
+                   return vs({p.w->bo.view()}, p.Vh(), p.w->n, nullptr, p.w->parts2.as<double>());
+               }),
+               s);
+    SParams sp;
+    sp.tol2 = prm.tol * prm.tol;
+    sp.delta2 = delta * delta;
+    sp.maxiter = prm.maxiter;
+    scalar_launch(S_BICG_INIT, SS(P, blas_nb(P), true, nullptr), sp, s);
+    launch_dslash_batch(DS(P, [&](const Prob &p) {
+                            return dcall(p.c, P64, 0, false, EPI_XPAY, p.w->bo.view(), p.w->bhat.view(),
+                                         p.w->be.view(), NOF, p.kappa, p.w->n, nullptr, nullptr);
+                        }),
+                        s);
+    vec_launch(V_ZERO, P64, VS(P, [&](const Prob &p) { return vs({p.w->x64.view()}, p.Vh(), p.w->n); }), s);
+    if (mixed) vec_launch(V_ZERO, prec, VS(P, [&](const Prob &p) { return vs({p.w->xlo.view()}, p.Vh(), p.w->n); }), s);
+    copy_launch(prec, P64, VS(P, [&](const Prob &p) { return vs({p.w->r.view(), p.w->bhat.view()}, p.Vh(), p.w->n); }),
+                s);
+    copy_launch(prec, prec, VS(P, [&](const Prob &p) { return vs({p.w->rh.view(), p.w->r.view()}, p.Vh(), p.w->n); }),
+                s);
+    vec_launch(V_ZERO, prec, VS(P, [&](const Prob &p) { return vs({p.w->p.view()}, p.Vh(), p.w->n); }), s);
+    vec_launch(V_ZERO, prec, VS(P, [&](const Prob &p) { return vs({p.w->v.view()}, p.Vh(), p.w->n); }), s);
+    vec_launch(V_DOT, prec, VS(P, [&](const Prob &p) {
+                   return vs({p.w->rh.view(), p.w->r.view()}, p.Vh(), p.w->n, nullptr, p.w->parts.as<double>());
+               }),
+               s);
+    SParams sr;
+    sr.np = 2;
+    sr.first = 1;
+    sr.mixed = mixed;
+    scalar_launch(S_BICG_RHO, SS(P, blas_nb(P), false, nullptr), sr, s);
 
     const int poll = parse_poll(prm);
-    std::vector<int> h;
     int it = 0;
     const int cap = prm.maxiter + poll + 8;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    bool first_chunk = true;
     while (it < cap) {
-        for (int k = 0; k < poll; ++k, ++it) {
-            k_bicg_p(P, w.p.view(), w.r.view(), w.v.view(), st, act, Vh, n, c.s);
-            launch_dslash(dcall(c, P, 1, false, EPI_PLAIN, w.p.view(), w.tmpo.view(), NOF, NOF, 1.0, n, nullptr, act),
-                          c.s);
-            int nbd = launch_dslash(dcall(c, P, 0, false, EPI_XPAY_DOT, w.tmpo.view(), w.v.view(), w.p.view(),
-                                          w.rh.view(), -k2, n, parts, act),
-                                    c.s);
-            k_bicg_alpha(st, act, n, parts, nbd, c.s);
-            k_bicg_s(P, w.r.view(), w.v.view(), st, act, Vh, n, c.s);
-            launch_dslash(dcall(c, P, 1, false, EPI_PLAIN, w.r.view(), w.tmpo.view(), NOF, NOF, 1.0, n, nullptr, act),
-                          c.s);
-            nbd = launch_dslash(dcall(c, P, 0, false, EPI_XPAY_TS, w.tmpo.view(), w.t.view(), w.r.view(), NOF, -k2, n,
-                                      parts, act),
-                                c.s);
-            k_bicg_omega(st, act, n, parts, nbd, c.s);
-            k_bicg_xr(P, xit, w.r.view(), w.p.view(), w.t.view(), w.rh.view(), st, act, Vh, n, parts, c.s);
-            k_bicg_rho(st, act, upd, nullptr, n, parts, nb, 3, 0, mixed, c.s);
+        if (prm.use_graph && !first_chunk) {
+            if (!exec) {
+                DL_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                for (int k = 0; k < poll; ++k) bicg_iteration(P, prec, mixed, s);
+                DL_HIP(hipStreamEndCapture(s, &graph));
+                DL_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+            }
+            DL_HIP(hipGraphLaunch(exec, s));
+            it += poll;
+        } else {
+            // the first chunk runs eagerly: it tunes every launch shape the graph will use
+            for (int k = 0; k < poll; ++k, ++it) bicg_iteration(P, prec, mixed, s);
+            first_chunk = false;
         }
         DL_HIP(hipGetLastError());
         // Poll point.  Right-hand sides flagged for a reliable update (converged,
@@ -615,28 +821,65 @@ void bicgstab_batch(const Ctx &c, double kappa, const dl_solve_params &prm, Solv
         // into the FP64 x and the FP64 residual bhat - Mhat x recomputed; where
         // the true residual disagrees with a claimed convergence the recursion
         // restarts from it.
-        if (count_host(w.upd, n, c.s, h) > 0) {
-            if (mixed) k_fold_x(w.x64.view(), P, w.xlo.view(), Vh, n, upd, c.s);
-            launch_dslash(
-                dcall(c, P64, 1, false, EPI_PLAIN, w.x64.view(), w.tmp64.view(), NOF, NOF, 1.0, n, nullptr, upd),
-                c.s);
-            int nb64 = launch_dslash(dcall(c, P64, 0, false, EPI_XMY_NRM, w.tmp64.view(), w.r64.view(), w.bhat.view(),
-                                           w.x64.view(), k2, n, parts2, upd),
-                                     c.s);
-            k_copy(P, w.r.view(), P64, w.r64.view(), Vh, n, upd, c.s);
-            k_true_residual(st, act, upd, rst, n, parts2, nullptr, nb64, 0, c.s);
-            k_copy(P, w.rh.view(), P, w.r.view(), Vh, n, rst, c.s);
-            k_zero(P, w.p.view(), Vh, n, rst, c.s);
-            k_zero(P, w.v.view(), Vh, n, rst, c.s);
-            k_dot_parts(P, w.rh.view(), w.r.view(), Vh, n, rst, parts, c.s);
-            k_bicg_rho(st, act, upd, rst, n, parts, nb, 2, 1, mixed, c.s);
+        if (count_all(P, true, s) > 0) {
+            if (mixed)
+                fold_launch(prec, VS(P, [&](const Prob &p) {
+                                return vs({p.w->x64.view(), p.w->xlo.view()}, p.Vh(), p.w->n, upd(p));
+                            }),
+                            s);
+            launch_dslash_batch(DS(P, [&](const Prob &p) {
+                                    return dcall(p.c, P64, 1, false, EPI_PLAIN, p.w->x64.view(), p.w->tmp64.view(),
+                                                 NOF, NOF, 1.0, p.w->n, nullptr, upd(p));
+                                }),
+                                s);
+            std::vector<int> nb64 = launch_dslash_batch(DS(P, [&](const Prob &p) {
+                                                            return dcall(p.c, P64, 0, false, EPI_XMY_NRM,
+                                                                         p.w->tmp64.view(), p.w->r64.view(),
+                                                                         p.w->bhat.view(), p.w->x64.view(),
+                                                                         p.kappa * p.kappa, p.w->n,
+                                                                         p.w->parts2.as<double>(), upd(p));
+                                                        }),
+                                                        s);
+            copy_launch(prec, P64, VS(P, [&](const Prob &p) {
+                            return vs({p.w->r.view(), p.w->r64.view()}, p.Vh(), p.w->n, upd(p));
+                        }),
+                        s);
+            // residual norms are in parts2 for this check
+            std::vector<SSeg> tr = SS(P, nb64, false, nullptr);
+            for (size_t k = 0; k < P.size(); ++k) tr[k].parts = P[k].w->parts2.as<double>();
+            scalar_launch(S_TRUE_RES, tr, SParams{}, s);
+            copy_launch(prec, prec, VS(P, [&](const Prob &p) {
+                            return vs({p.w->rh.view(), p.w->r.view()}, p.Vh(), p.w->n, mask_restart(p));
+                        }),
+                        s);
+            vec_launch(V_ZERO, prec,
+                       VS(P, [&](const Prob &p) { return vs({p.w->p.view()}, p.Vh(), p.w->n, mask_restart(p)); }), s);
+            vec_launch(V_ZERO, prec,
+                       VS(P, [&](const Prob &p) { return vs({p.w->v.view()}, p.Vh(), p.w->n, mask_restart(p)); }), s);
+            vec_launch(V_DOT, prec, VS(P, [&](const Prob &p) {
+                           return vs({p.w->rh.view(), p.w->r.view()}, p.Vh(), p.w->n, mask_restart(p),
+                                     p.w->parts.as<double>());
+                       }),
+                       s);
+            scalar_launch(S_BICG_RHO, SS(P, blas_nb(P), false, mask_restart), sr, s);
         }
-        if (count_host(w.act, n, c.s, h) == 0) break;
+        if (count_all(P, false, s) == 0) break;
     }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
     // x_o = b_o + kappa D_oe x_e
-    launch_dslash(
-        dcall(c, P64, 1, false, EPI_XPAY, w.x64.view(), w.xo.view(), w.bo.view(), NOF, kappa, n, nullptr, nullptr),
-        c.s);
+    launch_dslash_batch(DS(P, [&](const Prob &p) {
+                            return dcall(p.c, P64, 1, false, EPI_XPAY, p.w->x64.view(), p.w->xo.view(), p.w->bo.view(),
+                                         NOF, p.kappa, p.w->n, nullptr, nullptr);
+                        }),
+                        s);
+    DL_HIP(hipGetLastError());
+    if (cst) cst->join();
+}
+
+void bicgstab_batch(const Ctx &c, double kappa, const dl_solve_params &prm, SolveWork &w)
+{
+    bicgstab_multi({Prob{c, kappa, &w}}, prm, c.s);
 }
 
 // Full-lattice FP64 true residual |b - M x|^2 per right-hand side into out[n].
@@ -652,8 +895,17 @@ void true_residual_full(const Ctx &c, double kappa, SolveWork &w, std::vector<do
                         n, parts2, nullptr),
                   c.s);
     DevBuf sums(sizeof(double) * 2 * n);
-    k_sum_parts(parts, n, nbd, 1, sums.as<double>(), c.s);
-    k_sum_parts(parts2, n, nbd, 1, sums.as<double>() + n, c.s);
+    SSeg a;
+    a.parts = parts;
+    a.nblk = nbd;
+    a.nrhs = n;
+    a.out = sums.as<double>();
+    SParams sp;
+    sp.np = 1;
+    scalar_launch(S_SUM, {a}, sp, c.s);
+    a.parts = parts2;
+    a.out = sums.as<double>() + n;
+    scalar_launch(S_SUM, {a}, sp, c.s);
     std::vector<double> h(2 * n);
     DL_HIP(hipMemcpyAsync(h.data(), sums.p, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, c.s));
     DL_HIP(hipStreamSynchronize(c.s));
@@ -673,6 +925,15 @@ void cgnr_batch(const Ctx &c, double kappa, int iters, SolveWork &w)
     int *act = w.act.as<int>();
     double *parts = w.parts.as<double>();
     const double k2 = kappa * kappa;
+    auto sseg = [&](int nblk) {
+        SSeg a;
+        a.st = st;
+        a.act = act;
+        a.parts = parts;
+        a.nblk = nblk;
+        a.nrhs = n;
+        return std::vector<SSeg>{a};
+    };
     // bhat = b_e + kappa D_eo b_o ; r = Mhat^+ bhat ; x = 0 ; p = r
     launch_dslash(
         dcall(c, P, 0, false, EPI_XPAY, w.bo.view(), w.bhat.view(), w.be.view(), NOF, kappa, n, nullptr, nullptr),
@@ -681,7 +942,9 @@ void cgnr_batch(const Ctx &c, double kappa, int iters, SolveWork &w)
                   c.s);
     int nbd = launch_dslash(
         dcall(c, P, 0, true, EPI_XPAY_NRM, w.tmpo.view(), w.r.view(), w.bhat.view(), NOF, -k2, n, parts, nullptr), c.s);
-    k_cg_init(st, act, n, parts, nbd, iters, c.s);
+    SParams sp;
+    sp.maxiter = iters;
+    scalar_launch(S_CG_INIT, sseg(nbd), sp, c.s);
     k_zero(P, w.x64.view(), Vh, n, nullptr, c.s);
     k_copy(P, w.p.view(), P, w.r.view(), Vh, n, nullptr, c.s);
     for (int it = 0; it < iters; ++it) {
@@ -694,10 +957,10 @@ void cgnr_batch(const Ctx &c, double kappa, int iters, SolveWork &w)
         nbd = launch_dslash(
             dcall(c, P, 0, true, EPI_XPAY_DOT, w.tmpo.view(), w.v.view(), w.t.view(), w.p.view(), -k2, n, parts, act),
             c.s);
-        k_cg_alpha(st, act, n, parts, nbd, c.s);
-        k_cg_xr(P, w.x64.view(), w.r.view(), w.p.view(), w.v.view(), st, act, Vh, n, parts, c.s);
-        k_cg_beta(st, act, n, parts, nb, c.s);
-        k_cg_p(P, w.p.view(), w.r.view(), st, act, Vh, n, c.s);
+        scalar_launch(S_CG_ALPHA, sseg(nbd), SParams{}, c.s);
+        vec_launch(V_CG_XR, P, {vs({w.x64.view(), w.r.view(), w.p.view(), w.v.view()}, Vh, n, act, parts, st)}, c.s);
+        scalar_launch(S_CG_BETA, sseg(nb), SParams{}, c.s);
+        vec_launch(V_CG_P, P, {vs({w.p.view(), w.r.view()}, Vh, n, act, nullptr, st)}, c.s);
     }
     launch_dslash(
         dcall(c, P, 1, false, EPI_XPAY, w.x64.view(), w.xo.view(), w.bo.view(), NOF, kappa, n, nullptr, nullptr), c.s);
@@ -964,7 +1227,7 @@ int loops_run(dl_gauge G, double kappa, const dl_sources *src, const dl_solve_pa
         dA.alloc(A.size() * sizeof(double));
         DL_HIP(hipMemcpyAsync(dA.p, A.data(), dA.bytes, hipMemcpyHostToDevice, c.s));
         dgrad.alloc((size_t)4 * V * 9 * 16);
-        k_zero(P64, Field{dgrad.p, nullptr}, (int64_t)4 * V * 9 / 12, 1, nullptr, c.s);
+        k_zero(P64, Field{dgrad.p, nullptr}, (int64_t)4 * V * 9 / 12, 1, nullptr, c.s);  // [4][V][9] complex
     }
     int worst = DL_OK;
     std::vector<int64_t> hnoise;
@@ -1171,6 +1434,114 @@ extern "C" int dl_loops_link_grad(dl_gauge G, double kappa, const dl_sources *sr
         check_solver_for(G, *params);
         return loops_run(G, kappa, src, *params, gammas, n_gamma, MODE_GRAD, w, loops, grad, stats,
                          static_cast<hipStream_t>(stream), dloops);
+    });
+}
+
+// ====================================================================== batched lattices
+
+extern "C" int dl_batch_loops(int32_t n_lat, const dl_gauge *gauges, const double *kappas, const dl_sources *srcs,
+                              const dl_solve_params *params, const int32_t *gammas, int32_t n_gamma,
+                              double *const *loops, dl_solve_stats *const *stats, void *stream)
+{
+    return guarded([&]() {
+        DL_REQUIRE(n_lat >= 1 && n_lat <= MAXSEG, "dl_batch_loops: n_lat must be in [1, 4]");
+        DL_REQUIRE(gauges && kappas && srcs && loops, "dl_batch_loops: null pointer");
+        validate_params(params);
+        DL_REQUIRE(params->solver == DL_BICGSTAB, "dl_batch_loops: needs the tolerance-driven BiCGStab");
+        validate_gammas(gammas, n_gamma);
+        for (int l = 0; l < n_lat; ++l) {
+            DL_REQUIRE(gauges[l] && loops[l], "dl_batch_loops: null gauge or output pointer");
+            validate_sources(gauges[l]->lat, &srcs[l]);
+            check_solver_for(gauges[l], *params);
+        }
+        const dl_solve_params prm = *params;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        // noises per round, the same for every lattice, so that the round fits the workspace
+        size_t per_noise_all = 0;
+        int max_noise = 0;
+        for (int l = 0; l < n_lat; ++l) {
+            const int64_t Vh = gauges[l]->lat.Vh;
+            per_noise_all += (SolveWork::bytes_bicg(prm.prec, Vh) + (size_t)gauges[l]->lat.dims[3] * 32 * 8 + 16) *
+                             source_classes(&srcs[l]);
+            max_noise = std::max(max_noise, srcs[l].n_noise);
+        }
+        const int k = (int)std::max<int64_t>(1, std::min<int64_t>(max_noise, workspace_limit() / per_noise_all));
+        std::vector<double> gtab = gamma_table();
+        DevBuf dgam(gtab.size() * sizeof(double)), dgidx(sizeof(int) * n_gamma);
+        DL_HIP(hipMemcpyAsync(dgam.p, gtab.data(), dgam.bytes, hipMemcpyHostToDevice, s));
+        DL_HIP(hipMemcpyAsync(dgidx.p, gammas, dgidx.bytes, hipMemcpyHostToDevice, s));
+        std::vector<DevBuf> dloops(n_lat);
+        for (int l = 0; l < n_lat; ++l)
+            dloops[l].alloc((size_t)srcs[l].n_noise * n_gamma * gauges[l]->lat.dims[3] * 2 * sizeof(double));
+        int worst = DL_OK;
+        for (int n0 = 0; n0 < max_noise; n0 += k) {
+            std::vector<std::unique_ptr<SolveWork>> work;
+            std::vector<DevBuf> dnoise, dcls, dC;
+            std::vector<SourceSpec> spec;
+            std::vector<Prob> P;
+            std::vector<int> lat_of, r0_of, n_of;
+            for (int l = 0; l < n_lat; ++l) {
+                const int nn = std::min(k, srcs[l].n_noise - n0);
+                if (nn <= 0) continue;
+                const int ncls = source_classes(&srcs[l]);
+                const int n = nn * ncls;
+                dl_gauge G = gauges[l];
+                std::vector<int64_t> hn(n);
+                std::vector<int> hc(n);
+                for (int i = 0; i < n; ++i) {
+                    hn[i] = srcs[l].first_noise + n0 + i / ncls;
+                    hc[i] = i % ncls;
+                }
+                dnoise.emplace_back(sizeof(int64_t) * n);
+                dcls.emplace_back(sizeof(int) * n);
+                dC.emplace_back((size_t)n * G->lat.dims[3] * 32 * sizeof(double));
+                DL_HIP(hipMemcpyAsync(dnoise.back().p, hn.data(), dnoise.back().bytes, hipMemcpyHostToDevice, s));
+                DL_HIP(hipMemcpyAsync(dcls.back().p, hc.data(), dcls.back().bytes, hipMemcpyHostToDevice, s));
+                SourceSpec ss;
+                ss.kind = srcs[l].kind;
+                ss.scheme = srcs[l].kind == DL_SRC_POINT ? 0 : srcs[l].scheme;
+                ss.seed = srcs[l].seed;
+                ss.V = G->lat.V;
+                ss.point_site = srcs[l].point_site;
+                ss.noise = dnoise.back().as<int64_t>();
+                ss.cls = dcls.back().as<int>();
+                spec.push_back(ss);
+                work.emplace_back(new SolveWork);
+                SolveWork &w = *work.back();
+                w.alloc_bicg(prm.prec, n, G->lat.Vh);
+                Ctx c{G, G->lat.geom(), s};
+                k_source(P64, w.be.view(), 0, ss, c.g, n, s);
+                k_source(P64, w.bo.view(), 1, ss, c.g, n, s);
+                P.push_back(Prob{c, kappas[l], &w});
+                lat_of.push_back(l);
+                n_of.push_back(nn);
+            }
+            bicgstab_multi(P, prm, s);
+            for (size_t q = 0; q < P.size(); ++q) {
+                const int l = lat_of[q];
+                SolveWork &w = *P[q].w;
+                const int ncls = source_classes(&srcs[l]);
+                const int T = P[q].c.g.T;
+                std::vector<double> res2;
+                if (stats && stats[l]) true_residual_full(P[q].c, kappas[l], w, res2);
+                k_trace(P64, w.x64.view(), w.xo.view(), spec[q], P[q].c.g, w.n, dC[q].as<double>(), s);
+                k_gamma_contract(dC[q].as<double>(), n_of[q], ncls, T, dgam.as<double>(), dgidx.as<int>(), n_gamma,
+                                 dloops[l].as<double>() + (size_t)n0 * n_gamma * T * 2, s);
+                std::vector<dl_solve_stats> st(w.n);
+                fill_stats(w, res2, st.data(), s, false);
+                for (int i = 0; i < w.n; ++i) {
+                    if (stats && stats[l]) stats[l][(int64_t)n0 * ncls + i] = st[i];
+                    if (st[i].status != DL_OK && worst == DL_OK) worst = st[i].status;
+                }
+            }
+            DL_HIP(hipGetLastError());
+            DL_HIP(hipStreamSynchronize(s));
+        }
+        for (int l = 0; l < n_lat; ++l)
+            DL_HIP(hipMemcpyAsync(loops[l], dloops[l].p, dloops[l].bytes, hipMemcpyDeviceToHost, s));
+        DL_HIP(hipStreamSynchronize(s));
+        if (worst != DL_OK) g_err = "dl_batch_loops: at least one solve did not converge";
+        return worst;
     });
 }
 

@@ -2,11 +2,12 @@
 // their reductions, the per-right-hand-side scalar updates, and generic field
 // kernels (copy/convert, norms, dots, reliable-update folding).
 //
-// Reductions are deterministic: each block writes one partial per
-// right-hand side, and a one-wave-per-right-hand-side kernel sums the
-// partials in a fixed order.  Vector kernels run one thread per site with the
-// right-hand side on grid.y and return early for right-hand sides whose mask
-// flag is clear.
+// Every launch covers a batch of segments (one per lattice); a work item is
+// one (right-hand side, site block) of a segment, or one right-hand side for
+// the scalar kernels.  Reductions are deterministic: each site block writes
+// one partial per right-hand side, and a one-wave-per-right-hand-side kernel
+// sums the partials in a fixed order.  Items whose mask flag is clear return
+// at once.
 #include "dl_internal.hpp"
 
 namespace dl {
@@ -14,6 +15,7 @@ namespace dl {
 namespace {
 
 constexpr int BS = 256;
+constexpr int PERSIST = 8 * 32 * 16;  // grid cap of the streaming kernels (multiple of 8)
 
 template <typename R>
 __device__ __forceinline__ cx<R> ld_c(const double *p) { return {R(p[0]), R(p[1])}; }
@@ -44,39 +46,34 @@ __device__ __forceinline__ void cmul(const double a[2], const double b[2], doubl
     out[1] = im;
 }
 
-__global__ void bicg_init_kernel(KState *st, int *act, int *upd, const double *b2_parts_e, const double *b2_parts_o,
-                                 int nblk, double tol2, double delta2, int maxiter)
+__device__ void bicg_init(const SSeg &a, const SParams &p, int rhs)
 {
-    const int rhs = blockIdx.x;
-    double b2 = sum_parts(b2_parts_e, rhs, nblk, 1, 0);
-    if (b2_parts_o) b2 += sum_parts(b2_parts_o, rhs, nblk, 1, 0);
-    if (threadIdx.x == 0) {
-        KState s = {};
-        s.rho[0] = s.alpha[0] = s.omega[0] = 1.0;
-        s.b2 = b2;
-        s.stop2 = tol2 * b2;
-        s.delta2 = delta2;
-        s.maxiter = maxiter;
-        st[rhs] = s;
-        act[rhs] = b2 > 0 ? 1 : 0;
-        st[rhs].done = b2 > 0 ? 0 : 1;
-        upd[rhs] = 0;
-    }
+    double b2 = sum_parts(a.parts, rhs, a.nblk, 1, 0);
+    if (a.parts2) b2 += sum_parts(a.parts2, rhs, a.nblk, 1, 0);
+    if (threadIdx.x != 0) return;
+    KState s = {};
+    s.rho[0] = s.alpha[0] = s.omega[0] = 1.0;
+    s.b2 = b2;
+    s.stop2 = p.tol2 * b2;
+    s.delta2 = p.delta2;
+    s.maxiter = p.maxiter;
+    s.done = b2 > 0 ? 0 : 1;
+    a.st[rhs] = s;
+    a.act[rhs] = b2 > 0 ? 1 : 0;
+    a.upd[rhs] = 0;
 }
 
-// rho_new = (rhat, r) from parts[2] (+ |r|^2 in parts[2] of a 3-part layout when np = 3)
-__global__ void bicg_rho_kernel(KState *st, int *act, int *upd, const int *mask, const double *parts, int nblk,
-                                int np, int first, int mixed)
+// rho_new = (rhat, r) from partials [.., 2 or 3] (|r|^2 third when np = 3)
+__device__ void bicg_rho(const SSeg &a, const SParams &p, int rhs)
 {
-    const int rhs = blockIdx.x;
-    if (masked_off(mask, rhs)) return;
-    if (!first && !act[rhs]) return;
-    double rn[2] = {sum_parts(parts, rhs, nblk, np, 0), sum_parts(parts, rhs, nblk, np, 1)};
-    double rr = np == 3 ? sum_parts(parts, rhs, nblk, np, 2) : rn[0];
+    if (masked_off(a.mask, rhs)) return;
+    if (!p.first && !a.act[rhs]) return;
+    double rn[2] = {sum_parts(a.parts, rhs, a.nblk, p.np, 0), sum_parts(a.parts, rhs, a.nblk, p.np, 1)};
+    double rr = p.np == 3 ? sum_parts(a.parts, rhs, a.nblk, p.np, 2) : rn[0];
     if (threadIdx.x != 0) return;
-    KState s = st[rhs];
-    if (first) {
-        // restart: rho = alpha = omega = 1, p = v = 0, so beta = rho_new
+    KState s = a.st[rhs];
+    if (p.first) {
+        // (re)start: rho = alpha = omega = 1, p = v = 0, so beta = rho_new
         s.rho[0] = s.alpha[0] = s.omega[0] = 1.0;
         s.rho[1] = s.alpha[1] = s.omega[1] = 0.0;
         s.maxrr = rr;
@@ -92,522 +89,467 @@ __global__ void bicg_rho_kernel(KState *st, int *act, int *upd, const int *mask,
     s.rr = rr;
     if (!isfinite(rr) || !isfinite(s.beta[0]) || !isfinite(s.beta[1])) {
         s.nonfinite = 1;
-        act[rhs] = 0;
-        upd[rhs] = 0;
-    } else if (!first) {
+        a.act[rhs] = 0;
+        a.upd[rhs] = 0;
+    } else if (!p.first) {
         if (rr <= s.stop2 || s.iters >= s.maxiter || (rn[0] == 0 && rn[1] == 0)) {
             // converged (or out of iterations, or breakdown): check the FP64 true residual
-            act[rhs] = 0;
-            upd[rhs] = 1;
-        } else if (mixed && rr < s.delta2 * s.maxrr) {
-            upd[rhs] = 1;
+            a.act[rhs] = 0;
+            a.upd[rhs] = 1;
+        } else if (p.mixed && rr < s.delta2 * s.maxrr) {
+            a.upd[rhs] = 1;
         }
         if (rr > s.maxrr) s.maxrr = rr;
     }
-    st[rhs] = s;
+    a.st[rhs] = s;
 }
 
-__global__ void bicg_alpha_kernel(KState *st, const int *act, const double *parts, int nblk)
+__device__ void bicg_alpha(const SSeg &a, int rhs)
 {
-    const int rhs = blockIdx.x;
-    if (!act[rhs]) return;
-    double rv[2] = {sum_parts(parts, rhs, nblk, 2, 0), sum_parts(parts, rhs, nblk, 2, 1)};
+    if (!a.act[rhs]) return;
+    double rv[2] = {sum_parts(a.parts, rhs, a.nblk, 2, 0), sum_parts(a.parts, rhs, a.nblk, 2, 1)};
     if (threadIdx.x != 0) return;
-    KState s = st[rhs];
+    KState s = a.st[rhs];
     cdiv(s.rho, rv, s.alpha);
     if (!isfinite(s.alpha[0]) || !isfinite(s.alpha[1])) s.alpha[0] = s.alpha[1] = 0.0;
-    st[rhs] = s;
+    a.st[rhs] = s;
 }
 
-__global__ void bicg_omega_kernel(KState *st, const int *act, const double *parts, int nblk)
+__device__ void bicg_omega(const SSeg &a, int rhs)
 {
-    const int rhs = blockIdx.x;
-    if (!act[rhs]) return;
-    double ts[2] = {sum_parts(parts, rhs, nblk, 3, 0), sum_parts(parts, rhs, nblk, 3, 1)};
-    double tt = sum_parts(parts, rhs, nblk, 3, 2);
+    if (!a.act[rhs]) return;
+    double ts[2] = {sum_parts(a.parts, rhs, a.nblk, 3, 0), sum_parts(a.parts, rhs, a.nblk, 3, 1)};
+    double tt = sum_parts(a.parts, rhs, a.nblk, 3, 2);
     if (threadIdx.x != 0) return;
-    KState s = st[rhs];
+    KState s = a.st[rhs];
     if (tt > 0) {
         s.omega[0] = ts[0] / tt;
         s.omega[1] = ts[1] / tt;
     } else {
         s.omega[0] = s.omega[1] = 0.0;
     }
-    st[rhs] = s;
+    a.st[rhs] = s;
 }
 
-// after an FP64 residual recomputation (parts: |r_e|^2 [, |r_o|^2])
-__global__ void true_residual_kernel(KState *st, int *act, int *upd, int *restart, const double *parts_e,
-                                     const double *parts_o, int nblk, int final_check)
+// after an FP64 residual recomputation (parts: |r_e|^2 [, parts2: |r_o|^2])
+__device__ void true_residual(const SSeg &a, const SParams &p, int rhs)
 {
-    const int rhs = blockIdx.x;
-    if (!upd[rhs]) {
-        if (threadIdx.x == 0) restart[rhs] = 0;
+    if (!a.upd[rhs]) {
+        if (threadIdx.x == 0) a.restart[rhs] = 0;
         return;
     }
-    double r2 = sum_parts(parts_e, rhs, nblk, 1, 0);
-    if (parts_o) r2 += sum_parts(parts_o, rhs, nblk, 1, 0);
+    double r2 = sum_parts(a.parts, rhs, a.nblk, 1, 0);
+    if (a.parts2) r2 += sum_parts(a.parts2, rhs, a.nblk, 1, 0);
     if (threadIdx.x != 0) return;
-    KState s = st[rhs];
+    KState s = a.st[rhs];
     s.true2 = r2;
     s.updates += 1;
-    restart[rhs] = 0;
+    a.restart[rhs] = 0;
     if (!isfinite(r2)) {
         s.nonfinite = 1;
-        act[rhs] = 0;
+        a.act[rhs] = 0;
     } else if (r2 <= s.stop2) {
         s.done = 1;
-        act[rhs] = 0;
-    } else if (!act[rhs] && !final_check && s.iters < s.maxiter) {
+        a.act[rhs] = 0;
+    } else if (!a.act[rhs] && !p.final_check && s.iters < s.maxiter) {
         // the iterated residual claimed convergence but the true one disagrees:
         // restart the recursion from the true residual
-        act[rhs] = 1;
-        restart[rhs] = 1;
+        a.act[rhs] = 1;
+        a.restart[rhs] = 1;
     }
     s.maxrr = r2;
     s.rr = r2;
-    st[rhs] = s;
-    upd[rhs] = 0;
+    a.st[rhs] = s;
+    a.upd[rhs] = 0;
 }
 
-__global__ void cg_init_kernel(KState *st, int *act, const double *parts, int nblk, int iters)
+__device__ void cg_init(const SSeg &a, const SParams &p, int rhs)
 {
-    const int rhs = blockIdx.x;
-    double rr = sum_parts(parts, rhs, nblk, 1, 0);
-    if (threadIdx.x == 0) {
-        KState s = {};
-        s.rr = rr;
-        s.maxiter = iters;
-        st[rhs] = s;
-        act[rhs] = (rr > 0 && iters > 0) ? 1 : 0;
-    }
+    double rr = sum_parts(a.parts, rhs, a.nblk, 1, 0);
+    if (threadIdx.x != 0) return;
+    KState s = {};
+    s.rr = rr;
+    s.maxiter = p.maxiter;
+    a.st[rhs] = s;
+    a.act[rhs] = (rr > 0 && p.maxiter > 0) ? 1 : 0;
 }
 
 // alpha = rr / Re(p, q)
-__global__ void cg_alpha_kernel(KState *st, int *act, const double *parts, int nblk)
+__device__ void cg_alpha(const SSeg &a, int rhs)
 {
-    const int rhs = blockIdx.x;
-    if (!act[rhs]) return;
-    double pq = sum_parts(parts, rhs, nblk, 2, 0);
+    if (!a.act[rhs]) return;
+    double pq = sum_parts(a.parts, rhs, a.nblk, 2, 0);
     if (threadIdx.x != 0) return;
-    KState s = st[rhs];
+    KState s = a.st[rhs];
     if (pq > 0) {
         s.alpha[0] = s.rr / pq;
     } else {  // exact convergence: nothing left to do
         s.alpha[0] = 0;
-        act[rhs] = 0;
+        a.act[rhs] = 0;
     }
     s.alpha[1] = 0;
-    st[rhs] = s;
+    a.st[rhs] = s;
 }
 
-__global__ void cg_beta_kernel(KState *st, int *act, const double *parts, int nblk)
+__device__ void cg_beta(const SSeg &a, int rhs)
 {
-    const int rhs = blockIdx.x;
-    if (!act[rhs]) return;
-    double rr = sum_parts(parts, rhs, nblk, 1, 0);
+    if (!a.act[rhs]) return;
+    double rr = sum_parts(a.parts, rhs, a.nblk, 1, 0);
     if (threadIdx.x != 0) return;
-    KState s = st[rhs];
+    KState s = a.st[rhs];
     s.beta[0] = s.rr > 0 ? rr / s.rr : 0;
     s.beta[1] = 0;
     s.rr = rr;
     s.iters += 1;
-    if (s.iters >= s.maxiter || !(rr > 0)) act[rhs] = 0;
-    st[rhs] = s;
+    if (s.iters >= s.maxiter || !(rr > 0)) a.act[rhs] = 0;
+    a.st[rhs] = s;
 }
 
-__global__ void sum_parts_kernel(const double *parts, int nblk, int np, double *out)
+__device__ void sum_out(const SSeg &a, const SParams &p, int rhs)
 {
-    const int rhs = blockIdx.x;
-    for (int k = 0; k < np; ++k) {
-        double v = sum_parts(parts, rhs, nblk, np, k);
-        if (threadIdx.x == 0) out[rhs * np + k] = v;
+    for (int k = 0; k < p.np; ++k) {
+        double v = sum_parts(a.parts, rhs, a.nblk, p.np, k);
+        if (threadIdx.x == 0) a.out[rhs * p.np + k] = v;
     }
+}
+
+template <int OP>
+__global__ __launch_bounds__(64) void scalar_kernel(Segs<SSeg> B, SParams p)
+{
+    for_each_item(B, [&](const SSeg &a, int rhs) {
+        if constexpr (OP == S_BICG_INIT) bicg_init(a, p, rhs);
+        else if constexpr (OP == S_BICG_RHO) bicg_rho(a, p, rhs);
+        else if constexpr (OP == S_BICG_ALPHA) bicg_alpha(a, rhs);
+        else if constexpr (OP == S_BICG_OMEGA) bicg_omega(a, rhs);
+        else if constexpr (OP == S_TRUE_RES) true_residual(a, p, rhs);
+        else if constexpr (OP == S_CG_INIT) cg_init(a, p, rhs);
+        else if constexpr (OP == S_CG_ALPHA) cg_alpha(a, rhs);
+        else if constexpr (OP == S_CG_BETA) cg_beta(a, rhs);
+        else sum_out(a, p, rhs);
+    });
 }
 
 // ---------------------------------------------------------------- vector kernels
 
 template <int NP>
-__device__ __forceinline__ void write_parts(double v[NP], double *parts, int rhs)
+__device__ __forceinline__ void write_parts(double v[NP], double *red, double *parts, int rhs, int nb, int blk)
 {
-    __shared__ double red[NP * (BS / 64)];
     block_sum<NP>(v, red);
     if (threadIdx.x == 0)
 #pragma unroll
-        for (int k = 0; k < NP; ++k) parts[((int64_t)rhs * gridDim.x + blockIdx.x) * NP + k] = v[k];
+        for (int k = 0; k < NP; ++k) parts[((int64_t)rhs * nb + blk) * NP + k] = v[k];
+    __syncthreads();
 }
 
-// p = r + beta (p - omega v)
-template <typename S>
-__global__ __launch_bounds__(BS) void bicg_p_kernel(Field p, Field r, Field v, const KState *st, const int *act,
-                                                    int64_t Vh)
+// f[0..4] by operation:
+//   V_BICG_P  p = r + beta (p - omega v)                                        f: p, r, v
+//   V_BICG_S  r = r - alpha v                                                   f: r, v
+//   V_BICG_XR x += alpha p + omega s; r = s - omega t; parts (rhat, r), |r|^2   f: x, r(s), p, t, rhat
+//   V_CG_XR   x += alpha p; r -= alpha q; parts |r|^2                           f: x, r, p, q
+//   V_CG_P    p = r + beta p                                                    f: p, r
+//   V_ZERO    f0 = 0
+//   V_NORM2   parts |f0|^2
+//   V_DOT     parts (f0, f1)
+template <typename S, int OP>
+__device__ __forceinline__ void vec_item(const VSeg &a, int item, double *red)
 {
     using R = typename Fmt<S>::R;
-    const int rhs = blockIdx.y;
-    if (!act[rhs]) return;
-    const int64_t cb = (int64_t)blockIdx.x * BS + threadIdx.x;
-    if (cb >= Vh) return;
-    const cx<R> beta = ld_c<R>(st[rhs].beta), omega = ld_c<R>(st[rhs].omega);
-    cx<R> pv[12], rv[12], vv[12];
-    load_spinor<S>(p, Vh, rhs, cb, pv);
-    load_spinor<S>(r, Vh, rhs, cb, rv);
-    load_spinor<S>(v, Vh, rhs, cb, vv);
+    const int nb = (int)((a.Vh + BS - 1) / BS);
+    const int rhs = item / nb, blk = item - rhs * nb;
+    if (masked_off(a.mask, rhs)) return;
+    const int64_t Vh = a.Vh;
+    const int64_t cb = (int64_t)blk * BS + threadIdx.x;
+    const bool valid = cb < Vh;
+    if constexpr (OP == V_BICG_P) {
+        if (!valid) return;
+        const cx<R> beta = ld_c<R>(a.st[rhs].beta), omega = ld_c<R>(a.st[rhs].omega);
+        cx<R> pv[12], rv[12], vv[12];
+        load_spinor<S>(a.f[0], Vh, rhs, cb, pv);
+        load_spinor<S>(a.f[1], Vh, rhs, cb, rv);
+        load_spinor<S>(a.f[2], Vh, rhs, cb, vv);
 #pragma unroll
-    for (int e = 0; e < 12; ++e) pv[e] = rv[e] + beta * (pv[e] - omega * vv[e]);
-    store_spinor<S>(p, Vh, rhs, cb, pv);
-}
-
-// r = r - alpha v   (r becomes s)
-template <typename S>
-__global__ __launch_bounds__(BS) void bicg_s_kernel(Field r, Field v, const KState *st, const int *act, int64_t Vh)
-{
-    using R = typename Fmt<S>::R;
-    const int rhs = blockIdx.y;
-    if (!act[rhs]) return;
-    const int64_t cb = (int64_t)blockIdx.x * BS + threadIdx.x;
-    if (cb >= Vh) return;
-    const cx<R> alpha = ld_c<R>(st[rhs].alpha);
-    cx<R> rv[12], vv[12];
-    load_spinor<S>(r, Vh, rhs, cb, rv);
-    load_spinor<S>(v, Vh, rhs, cb, vv);
+        for (int e = 0; e < 12; ++e) pv[e] = rv[e] + beta * (pv[e] - omega * vv[e]);
+        store_spinor<S>(a.f[0], Vh, rhs, cb, pv);
+    } else if constexpr (OP == V_BICG_S) {
+        if (!valid) return;
+        const cx<R> alpha = ld_c<R>(a.st[rhs].alpha);
+        cx<R> rv[12], vv[12];
+        load_spinor<S>(a.f[0], Vh, rhs, cb, rv);
+        load_spinor<S>(a.f[1], Vh, rhs, cb, vv);
 #pragma unroll
-    for (int e = 0; e < 12; ++e) rv[e] = rv[e] - alpha * vv[e];
-    store_spinor<S>(r, Vh, rhs, cb, rv);
-}
-
-// x += alpha p + omega s;  r = s - omega t;  partials (rhat, r), |r|^2
-template <typename S>
-__global__ __launch_bounds__(BS) void bicg_xr_kernel(Field x, Field r, Field p, Field t, Field rh, const KState *st,
-                                                     const int *act, int64_t Vh, double *parts)
-{
-    using R = typename Fmt<S>::R;
-    const int rhs = blockIdx.y;
-    if (!act[rhs]) return;
-    const int64_t cb = (int64_t)blockIdx.x * BS + threadIdx.x;
-    double part[3] = {0, 0, 0};
-    if (cb < Vh) {
-        const cx<R> alpha = ld_c<R>(st[rhs].alpha), omega = ld_c<R>(st[rhs].omega);
-        cx<R> xv[12], sv[12], pv[12], tv[12], hv[12];
-        load_spinor<S>(x, Vh, rhs, cb, xv);
-        load_spinor<S>(r, Vh, rhs, cb, sv);
-        load_spinor<S>(p, Vh, rhs, cb, pv);
-        load_spinor<S>(t, Vh, rhs, cb, tv);
-        load_spinor<S>(rh, Vh, rhs, cb, hv);
+        for (int e = 0; e < 12; ++e) rv[e] = rv[e] - alpha * vv[e];
+        store_spinor<S>(a.f[0], Vh, rhs, cb, rv);
+    } else if constexpr (OP == V_BICG_XR) {
+        double part[3] = {0, 0, 0};
+        if (valid) {
+            const cx<R> alpha = ld_c<R>(a.st[rhs].alpha), omega = ld_c<R>(a.st[rhs].omega);
+            cx<R> xv[12], sv[12], pv[12], tv[12], hv[12];
+            load_spinor<S>(a.f[0], Vh, rhs, cb, xv);
+            load_spinor<S>(a.f[1], Vh, rhs, cb, sv);
+            load_spinor<S>(a.f[2], Vh, rhs, cb, pv);
+            load_spinor<S>(a.f[3], Vh, rhs, cb, tv);
+            load_spinor<S>(a.f[4], Vh, rhs, cb, hv);
 #pragma unroll
-        for (int e = 0; e < 12; ++e) {
-            xv[e] = xv[e] + alpha * pv[e] + omega * sv[e];
-            sv[e] = sv[e] - omega * tv[e];
-            part[0] += (double)hv[e].re * sv[e].re + (double)hv[e].im * sv[e].im;
-            part[1] += (double)hv[e].re * sv[e].im - (double)hv[e].im * sv[e].re;
-            part[2] += (double)sv[e].re * sv[e].re + (double)sv[e].im * sv[e].im;
+            for (int e = 0; e < 12; ++e) {
+                xv[e] = xv[e] + alpha * pv[e] + omega * sv[e];
+                sv[e] = sv[e] - omega * tv[e];
+                part[0] += (double)hv[e].re * sv[e].re + (double)hv[e].im * sv[e].im;
+                part[1] += (double)hv[e].re * sv[e].im - (double)hv[e].im * sv[e].re;
+                part[2] += (double)sv[e].re * sv[e].re + (double)sv[e].im * sv[e].im;
+            }
+            store_spinor<S>(a.f[0], Vh, rhs, cb, xv);
+            store_spinor<S>(a.f[1], Vh, rhs, cb, sv);
         }
-        store_spinor<S>(x, Vh, rhs, cb, xv);
-        store_spinor<S>(r, Vh, rhs, cb, sv);
-    }
-    write_parts<3>(part, parts, rhs);
-}
-
-// x += alpha p;  r -= alpha q;  partial |r|^2
-template <typename S>
-__global__ __launch_bounds__(BS) void cg_xr_kernel(Field x, Field r, Field p, Field q, const KState *st,
-                                                   const int *act, int64_t Vh, double *parts)
-{
-    using R = typename Fmt<S>::R;
-    const int rhs = blockIdx.y;
-    if (!act[rhs]) return;
-    const int64_t cb = (int64_t)blockIdx.x * BS + threadIdx.x;
-    double part[1] = {0};
-    if (cb < Vh) {
-        const R alpha = R(st[rhs].alpha[0]);
-        cx<R> xv[12], rv[12], pv[12], qv[12];
-        load_spinor<S>(x, Vh, rhs, cb, xv);
-        load_spinor<S>(r, Vh, rhs, cb, rv);
-        load_spinor<S>(p, Vh, rhs, cb, pv);
-        load_spinor<S>(q, Vh, rhs, cb, qv);
+        write_parts<3>(part, red, a.parts, rhs, nb, blk);
+    } else if constexpr (OP == V_CG_XR) {
+        double part[1] = {0};
+        if (valid) {
+            const R alpha = R(a.st[rhs].alpha[0]);
+            cx<R> xv[12], rv[12], pv[12], qv[12];
+            load_spinor<S>(a.f[0], Vh, rhs, cb, xv);
+            load_spinor<S>(a.f[1], Vh, rhs, cb, rv);
+            load_spinor<S>(a.f[2], Vh, rhs, cb, pv);
+            load_spinor<S>(a.f[3], Vh, rhs, cb, qv);
 #pragma unroll
-        for (int e = 0; e < 12; ++e) {
-            xv[e] = xv[e] + alpha * pv[e];
-            rv[e] = rv[e] - alpha * qv[e];
-            part[0] += (double)rv[e].re * rv[e].re + (double)rv[e].im * rv[e].im;
+            for (int e = 0; e < 12; ++e) {
+                xv[e] = xv[e] + alpha * pv[e];
+                rv[e] = rv[e] - alpha * qv[e];
+                part[0] += (double)rv[e].re * rv[e].re + (double)rv[e].im * rv[e].im;
+            }
+            store_spinor<S>(a.f[0], Vh, rhs, cb, xv);
+            store_spinor<S>(a.f[1], Vh, rhs, cb, rv);
         }
-        store_spinor<S>(x, Vh, rhs, cb, xv);
-        store_spinor<S>(r, Vh, rhs, cb, rv);
-    }
-    write_parts<1>(part, parts, rhs);
-}
-
-// p = r + beta p
-template <typename S>
-__global__ __launch_bounds__(BS) void cg_p_kernel(Field p, Field r, const KState *st, const int *act, int64_t Vh)
-{
-    using R = typename Fmt<S>::R;
-    const int rhs = blockIdx.y;
-    if (!act[rhs]) return;
-    const int64_t cb = (int64_t)blockIdx.x * BS + threadIdx.x;
-    if (cb >= Vh) return;
-    const R beta = R(st[rhs].beta[0]);
-    cx<R> pv[12], rv[12];
-    load_spinor<S>(p, Vh, rhs, cb, pv);
-    load_spinor<S>(r, Vh, rhs, cb, rv);
+        write_parts<1>(part, red, a.parts, rhs, nb, blk);
+    } else if constexpr (OP == V_CG_P) {
+        if (!valid) return;
+        const R beta = R(a.st[rhs].beta[0]);
+        cx<R> pv[12], rv[12];
+        load_spinor<S>(a.f[0], Vh, rhs, cb, pv);
+        load_spinor<S>(a.f[1], Vh, rhs, cb, rv);
 #pragma unroll
-    for (int e = 0; e < 12; ++e) pv[e] = rv[e] + beta * pv[e];
-    store_spinor<S>(p, Vh, rhs, cb, pv);
+        for (int e = 0; e < 12; ++e) pv[e] = rv[e] + beta * pv[e];
+        store_spinor<S>(a.f[0], Vh, rhs, cb, pv);
+    } else if constexpr (OP == V_ZERO) {
+        if (!valid) return;
+        cx<R> v[12];
+#pragma unroll
+        for (int e = 0; e < 12; ++e) v[e] = {R(0), R(0)};
+        store_spinor<S>(a.f[0], Vh, rhs, cb, v);
+    } else if constexpr (OP == V_NORM2) {
+        double part[1] = {0};
+        if (valid) {
+            cx<R> v[12];
+            load_spinor<S>(a.f[0], Vh, rhs, cb, v);
+#pragma unroll
+            for (int e = 0; e < 12; ++e) part[0] += (double)v[e].re * v[e].re + (double)v[e].im * v[e].im;
+        }
+        write_parts<1>(part, red, a.parts, rhs, nb, blk);
+    } else if constexpr (OP == V_DOT) {
+        double part[2] = {0, 0};
+        if (valid) {
+            cx<R> av[12], bv[12];
+            load_spinor<S>(a.f[0], Vh, rhs, cb, av);
+            load_spinor<S>(a.f[1], Vh, rhs, cb, bv);
+#pragma unroll
+            for (int e = 0; e < 12; ++e) {
+                part[0] += (double)av[e].re * bv[e].re + (double)av[e].im * bv[e].im;
+                part[1] += (double)av[e].re * bv[e].im - (double)av[e].im * bv[e].re;
+            }
+        }
+        write_parts<2>(part, red, a.parts, rhs, nb, blk);
+    }
 }
 
+template <typename S, int OP>
+__global__ __launch_bounds__(BS) void vec_kernel(Segs<VSeg> B)
+{
+    __shared__ double red[3 * (BS / 64)];
+    for_each_item(B, [&](const VSeg &a, int item) { vec_item<S, OP>(a, item, red); });
+}
+
+// dst (f0, precision SD) = src (f1, precision SS)
 template <typename SD, typename SS>
-__global__ __launch_bounds__(BS) void copy_kernel(Field dst, Field src, const int *mask, int64_t Vh)
+__global__ __launch_bounds__(BS) void copy_kernel(Segs<VSeg> B)
 {
     using RD = typename Fmt<SD>::R;
     using RS = typename Fmt<SS>::R;
-    const int rhs = blockIdx.y;
-    if (masked_off(mask, rhs)) return;
-    const int64_t cb = (int64_t)blockIdx.x * BS + threadIdx.x;
-    if (cb >= Vh) return;
-    cx<RS> v[12];
-    cx<RD> w[12];
-    load_spinor<SS>(src, Vh, rhs, cb, v);
+    for_each_item(B, [&](const VSeg &a, int item) {
+        const int nb = (int)((a.Vh + BS - 1) / BS);
+        const int rhs = item / nb, blk = item - rhs * nb;
+        if (masked_off(a.mask, rhs)) return;
+        const int64_t cb = (int64_t)blk * BS + threadIdx.x;
+        if (cb >= a.Vh) return;
+        cx<RS> v[12];
+        cx<RD> w[12];
+        load_spinor<SS>(a.f[1], a.Vh, rhs, cb, v);
 #pragma unroll
-    for (int e = 0; e < 12; ++e) w[e] = {RD(v[e].re), RD(v[e].im)};
-    store_spinor<SD>(dst, Vh, rhs, cb, w);
+        for (int e = 0; e < 12; ++e) w[e] = {RD(v[e].re), RD(v[e].im)};
+        store_spinor<SD>(a.f[0], a.Vh, rhs, cb, w);
+    });
 }
 
+// f0 (FP64) += f1 (precision S); f1 = 0      (reliable update of x)
 template <typename S>
-__global__ __launch_bounds__(BS) void zero_kernel(Field f, const int *mask, int64_t Vh)
+__global__ __launch_bounds__(BS) void fold_kernel(Segs<VSeg> B)
 {
     using R = typename Fmt<S>::R;
-    const int rhs = blockIdx.y;
-    if (masked_off(mask, rhs)) return;
-    const int64_t cb = (int64_t)blockIdx.x * BS + threadIdx.x;
-    if (cb >= Vh) return;
-    cx<R> v[12];
-#pragma unroll
-    for (int e = 0; e < 12; ++e) v[e] = {R(0), R(0)};
-    store_spinor<S>(f, Vh, rhs, cb, v);
-}
-
-// x64 += xlo; xlo = 0   (masked by the update flags)
-template <typename S>
-__global__ __launch_bounds__(BS) void fold_kernel(Field x64, Field xlo, const int *mask, int64_t Vh)
-{
-    using R = typename Fmt<S>::R;
-    const int rhs = blockIdx.y;
-    if (masked_off(mask, rhs)) return;
-    const int64_t cb = (int64_t)blockIdx.x * BS + threadIdx.x;
-    if (cb >= Vh) return;
-    cx<double> xv[12];
-    cx<R> lv[12];
-    load_spinor<double>(x64, Vh, rhs, cb, xv);
-    load_spinor<S>(xlo, Vh, rhs, cb, lv);
-#pragma unroll
-    for (int e = 0; e < 12; ++e) {
-        xv[e].re += (double)lv[e].re;
-        xv[e].im += (double)lv[e].im;
-        lv[e] = {R(0), R(0)};
-    }
-    store_spinor<double>(x64, Vh, rhs, cb, xv);
-    store_spinor<S>(xlo, Vh, rhs, cb, lv);
-}
-
-template <typename S>
-__global__ __launch_bounds__(BS) void norm2_kernel(Field f, const int *mask, int64_t Vh, double *parts)
-{
-    using R = typename Fmt<S>::R;
-    const int rhs = blockIdx.y;
-    if (masked_off(mask, rhs)) return;
-    const int64_t cb = (int64_t)blockIdx.x * BS + threadIdx.x;
-    double part[1] = {0};
-    if (cb < Vh) {
-        cx<R> v[12];
-        load_spinor<S>(f, Vh, rhs, cb, v);
-#pragma unroll
-        for (int e = 0; e < 12; ++e) part[0] += (double)v[e].re * v[e].re + (double)v[e].im * v[e].im;
-    }
-    write_parts<1>(part, parts, rhs);
-}
-
-template <typename S>
-__global__ __launch_bounds__(BS) void dot_kernel(Field a, Field b, const int *mask, int64_t Vh, double *parts)
-{
-    using R = typename Fmt<S>::R;
-    const int rhs = blockIdx.y;
-    if (masked_off(mask, rhs)) return;
-    const int64_t cb = (int64_t)blockIdx.x * BS + threadIdx.x;
-    double part[2] = {0, 0};
-    if (cb < Vh) {
-        cx<R> av[12], bv[12];
-        load_spinor<S>(a, Vh, rhs, cb, av);
-        load_spinor<S>(b, Vh, rhs, cb, bv);
+    for_each_item(B, [&](const VSeg &a, int item) {
+        const int nb = (int)((a.Vh + BS - 1) / BS);
+        const int rhs = item / nb, blk = item - rhs * nb;
+        if (masked_off(a.mask, rhs)) return;
+        const int64_t cb = (int64_t)blk * BS + threadIdx.x;
+        if (cb >= a.Vh) return;
+        cx<double> xv[12];
+        cx<R> lv[12];
+        load_spinor<double>(a.f[0], a.Vh, rhs, cb, xv);
+        load_spinor<S>(a.f[1], a.Vh, rhs, cb, lv);
 #pragma unroll
         for (int e = 0; e < 12; ++e) {
-            part[0] += (double)av[e].re * bv[e].re + (double)av[e].im * bv[e].im;
-            part[1] += (double)av[e].re * bv[e].im - (double)av[e].im * bv[e].re;
+            xv[e].re += (double)lv[e].re;
+            xv[e].im += (double)lv[e].im;
+            lv[e] = {R(0), R(0)};
         }
-    }
-    write_parts<2>(part, parts, rhs);
+        store_spinor<double>(a.f[0], a.Vh, rhs, cb, xv);
+        store_spinor<S>(a.f[1], a.Vh, rhs, cb, lv);
+    });
 }
 
-__global__ __launch_bounds__(BS) void sub_kernel(Field dst, Field a, Field b, const int *mask, int64_t Vh)
+// f0 = f1 - f2 (FP64)
+__global__ __launch_bounds__(BS) void sub_kernel(Segs<VSeg> B)
 {
-    const int rhs = blockIdx.y;
-    if (masked_off(mask, rhs)) return;
-    const int64_t cb = (int64_t)blockIdx.x * BS + threadIdx.x;
-    if (cb >= Vh) return;
-    cx<double> av[12], bv[12];
-    load_spinor<double>(a, Vh, rhs, cb, av);
-    load_spinor<double>(b, Vh, rhs, cb, bv);
+    for_each_item(B, [&](const VSeg &a, int item) {
+        const int nb = (int)((a.Vh + BS - 1) / BS);
+        const int rhs = item / nb, blk = item - rhs * nb;
+        if (masked_off(a.mask, rhs)) return;
+        const int64_t cb = (int64_t)blk * BS + threadIdx.x;
+        if (cb >= a.Vh) return;
+        cx<double> av[12], bv[12];
+        load_spinor<double>(a.f[1], a.Vh, rhs, cb, av);
+        load_spinor<double>(a.f[2], a.Vh, rhs, cb, bv);
 #pragma unroll
-    for (int e = 0; e < 12; ++e) av[e] = av[e] - bv[e];
-    store_spinor<double>(dst, Vh, rhs, cb, av);
+        for (int e = 0; e < 12; ++e) av[e] = av[e] - bv[e];
+        store_spinor<double>(a.f[0], a.Vh, rhs, cb, av);
+    });
 }
 
-#define DL_DISPATCH(prec, NAME, ...)                                                                    \
-    do {                                                                                                \
-        switch (prec) {                                                                                 \
-        case P64: hipLaunchKernelGGL(NAME<double>, __VA_ARGS__); break;                                 \
-        case P32: hipLaunchKernelGGL(NAME<float>, __VA_ARGS__); break;                                  \
-        case P16: hipLaunchKernelGGL(NAME<__half>, __VA_ARGS__); break;                                 \
-        default: hipLaunchKernelGGL(NAME<__hip_bfloat16>, __VA_ARGS__); break;                          \
-        }                                                                                               \
-    } while (0)
-
-double vec_bytes(int prec, int64_t Vh, int nrhs, int nvec)
+template <typename A>
+Segs<A> make_segs(const std::vector<A> &v, int (*items)(const A &))
 {
-    double per = (double)Vh * 12 * elem_bytes(prec) + (prec == P16 ? 4.0 * Vh : 0.0);
-    return per * nrhs * nvec;
+    Segs<A> B;
+    if (v.empty() || v.size() > (size_t)MAXSEG) throw Error{DL_EINVAL, "internal: segment count out of range"};
+    B.n = (int)v.size();
+    B.prefix[0] = 0;
+    for (int k = 0; k < B.n; ++k) {
+        B.a[k] = v[k];
+        B.prefix[k + 1] = B.prefix[k] + items(v[k]);
+    }
+    return B;
+}
+
+int vec_items(const VSeg &a) { return (int)((a.Vh + BS - 1) / BS) * a.nrhs; }
+int scalar_items(const SSeg &a) { return a.nrhs; }
+
+int grid_for(int total, int cap) { return total > cap ? cap : total; }
+
+double vec_bytes(int prec, const std::vector<VSeg> &segs, int nvec)
+{
+    double b = 0;
+    for (const VSeg &a : segs) b += ((double)a.Vh * 12 * elem_bytes(prec) + (prec == P16 ? 4.0 * a.Vh : 0.0)) * a.nrhs;
+    return b * nvec;
+}
+
+template <int OP>
+void vec_dispatch(int prec, const Segs<VSeg> &B, int grid, hipStream_t s)
+{
+    switch (prec) {
+    case P64: hipLaunchKernelGGL((vec_kernel<double, OP>), dim3(grid), dim3(BS), 0, s, B); break;
+    case P32: hipLaunchKernelGGL((vec_kernel<float, OP>), dim3(grid), dim3(BS), 0, s, B); break;
+    case P16: hipLaunchKernelGGL((vec_kernel<__half, OP>), dim3(grid), dim3(BS), 0, s, B); break;
+    default: hipLaunchKernelGGL((vec_kernel<__hip_bfloat16, OP>), dim3(grid), dim3(BS), 0, s, B); break;
+    }
+}
+
+template <typename SD>
+void copy_from(int prec_src, const Segs<VSeg> &B, int grid, hipStream_t s)
+{
+    switch (prec_src) {
+    case P64: hipLaunchKernelGGL((copy_kernel<SD, double>), dim3(grid), dim3(BS), 0, s, B); break;
+    case P32: hipLaunchKernelGGL((copy_kernel<SD, float>), dim3(grid), dim3(BS), 0, s, B); break;
+    case P16: hipLaunchKernelGGL((copy_kernel<SD, __half>), dim3(grid), dim3(BS), 0, s, B); break;
+    default: hipLaunchKernelGGL((copy_kernel<SD, __hip_bfloat16>), dim3(grid), dim3(BS), 0, s, B); break;
+    }
 }
 
 }  // namespace
 
 int blas_blocks(int64_t Vh) { return (int)((Vh + BS - 1) / BS); }
 
-static dim3 vgrid(int64_t Vh, int nrhs) { return dim3(blas_blocks(Vh), nrhs); }
-
-// ---------------------------------------------------------------- scalar launches
-
-void k_bicg_init(KState *st, int *act, int *upd, int nrhs, const double *b2_parts_e, const double *b2_parts_o,
-                 int nblk, double tol2, double delta2, int maxiter, hipStream_t s)
+void scalar_launch(int op, const std::vector<SSeg> &segs, const SParams &p, hipStream_t s)
 {
-    hipLaunchKernelGGL(bicg_init_kernel, dim3(nrhs), dim3(64), 0, s, st, act, upd, b2_parts_e, b2_parts_o, nblk, tol2,
-                       delta2, maxiter);
-}
-void k_bicg_rho(KState *st, int *act, int *upd, const int *mask, int nrhs, const double *parts, int nblk, int np,
-                int first, int mixed, hipStream_t s)
-{
-    hipLaunchKernelGGL(bicg_rho_kernel, dim3(nrhs), dim3(64), 0, s, st, act, upd, mask, parts, nblk, np, first, mixed);
-}
-void k_bicg_alpha(KState *st, const int *act, int nrhs, const double *parts, int nblk, hipStream_t s)
-{
-    hipLaunchKernelGGL(bicg_alpha_kernel, dim3(nrhs), dim3(64), 0, s, st, act, parts, nblk);
-}
-void k_bicg_omega(KState *st, const int *act, int nrhs, const double *parts, int nblk, hipStream_t s)
-{
-    hipLaunchKernelGGL(bicg_omega_kernel, dim3(nrhs), dim3(64), 0, s, st, act, parts, nblk);
-}
-void k_true_residual(KState *st, int *act, int *upd, int *restart, int nrhs, const double *parts_e,
-                     const double *parts_o, int nblk, int final_check, hipStream_t s)
-{
-    hipLaunchKernelGGL(true_residual_kernel, dim3(nrhs), dim3(64), 0, s, st, act, upd, restart, parts_e, parts_o,
-                       nblk, final_check);
-}
-void k_cg_init(KState *st, int *act, int nrhs, const double *parts, int nblk, int iters, hipStream_t s)
-{
-    hipLaunchKernelGGL(cg_init_kernel, dim3(nrhs), dim3(64), 0, s, st, act, parts, nblk, iters);
-}
-void k_cg_alpha(KState *st, int *act, int nrhs, const double *parts, int nblk, hipStream_t s)
-{
-    hipLaunchKernelGGL(cg_alpha_kernel, dim3(nrhs), dim3(64), 0, s, st, act, parts, nblk);
-}
-void k_cg_beta(KState *st, int *act, int nrhs, const double *parts, int nblk, hipStream_t s)
-{
-    hipLaunchKernelGGL(cg_beta_kernel, dim3(nrhs), dim3(64), 0, s, st, act, parts, nblk);
-}
-void k_sum_parts(const double *parts, int nrhs, int nblk, int nparts, double *out, hipStream_t s)
-{
-    hipLaunchKernelGGL(sum_parts_kernel, dim3(nrhs), dim3(64), 0, s, parts, nblk, nparts, out);
-}
-
-// ---------------------------------------------------------------- vector launches
-
-void k_bicg_p(int prec, Field p, Field r, Field v, const KState *st, const int *act, int64_t Vh, int nrhs,
-              hipStream_t s)
-{
-    ProfScope ps(PROF_BLAS, vec_bytes(prec, Vh, nrhs, 4), s);
-    DL_DISPATCH(prec, bicg_p_kernel, vgrid(Vh, nrhs), dim3(BS), 0, s, p, r, v, st, act, Vh);
-}
-void k_bicg_s(int prec, Field r, Field v, const KState *st, const int *act, int64_t Vh, int nrhs, hipStream_t s)
-{
-    ProfScope ps(PROF_BLAS, vec_bytes(prec, Vh, nrhs, 3), s);
-    DL_DISPATCH(prec, bicg_s_kernel, vgrid(Vh, nrhs), dim3(BS), 0, s, r, v, st, act, Vh);
-}
-void k_bicg_xr(int prec, Field x, Field r, Field p, Field t, Field rh, const KState *st, const int *act, int64_t Vh,
-               int nrhs, double *parts, hipStream_t s)
-{
-    ProfScope ps(PROF_BLAS, vec_bytes(prec, Vh, nrhs, 7), s);
-    DL_DISPATCH(prec, bicg_xr_kernel, vgrid(Vh, nrhs), dim3(BS), 0, s, x, r, p, t, rh, st, act, Vh, parts);
-}
-void k_cg_xr(int prec, Field x, Field r, Field p, Field q, const KState *st, const int *act, int64_t Vh, int nrhs,
-             double *parts, hipStream_t s)
-{
-    ProfScope ps(PROF_BLAS, vec_bytes(prec, Vh, nrhs, 6), s);
-    DL_DISPATCH(prec, cg_xr_kernel, vgrid(Vh, nrhs), dim3(BS), 0, s, x, r, p, q, st, act, Vh, parts);
-}
-void k_cg_p(int prec, Field p, Field r, const KState *st, const int *act, int64_t Vh, int nrhs, hipStream_t s)
-{
-    ProfScope ps(PROF_BLAS, vec_bytes(prec, Vh, nrhs, 3), s);
-    DL_DISPATCH(prec, cg_p_kernel, vgrid(Vh, nrhs), dim3(BS), 0, s, p, r, st, act, Vh);
-}
-
-template <typename SD>
-static void copy_from(int prec_src, Field dst, Field src, const int *mask, int64_t Vh, int nrhs, hipStream_t s)
-{
-    dim3 g = vgrid(Vh, nrhs);
-    switch (prec_src) {
-    case P64: hipLaunchKernelGGL((copy_kernel<SD, double>), g, dim3(BS), 0, s, dst, src, mask, Vh); break;
-    case P32: hipLaunchKernelGGL((copy_kernel<SD, float>), g, dim3(BS), 0, s, dst, src, mask, Vh); break;
-    case P16: hipLaunchKernelGGL((copy_kernel<SD, __half>), g, dim3(BS), 0, s, dst, src, mask, Vh); break;
-    default: hipLaunchKernelGGL((copy_kernel<SD, __hip_bfloat16>), g, dim3(BS), 0, s, dst, src, mask, Vh); break;
+    Segs<SSeg> B = make_segs(segs, scalar_items);
+    const int grid = grid_for(B.prefix[B.n], PERSIST);
+    switch (op) {
+    case S_BICG_INIT: hipLaunchKernelGGL(scalar_kernel<S_BICG_INIT>, dim3(grid), dim3(64), 0, s, B, p); break;
+    case S_BICG_RHO: hipLaunchKernelGGL(scalar_kernel<S_BICG_RHO>, dim3(grid), dim3(64), 0, s, B, p); break;
+    case S_BICG_ALPHA: hipLaunchKernelGGL(scalar_kernel<S_BICG_ALPHA>, dim3(grid), dim3(64), 0, s, B, p); break;
+    case S_BICG_OMEGA: hipLaunchKernelGGL(scalar_kernel<S_BICG_OMEGA>, dim3(grid), dim3(64), 0, s, B, p); break;
+    case S_TRUE_RES: hipLaunchKernelGGL(scalar_kernel<S_TRUE_RES>, dim3(grid), dim3(64), 0, s, B, p); break;
+    case S_CG_INIT: hipLaunchKernelGGL(scalar_kernel<S_CG_INIT>, dim3(grid), dim3(64), 0, s, B, p); break;
+    case S_CG_ALPHA: hipLaunchKernelGGL(scalar_kernel<S_CG_ALPHA>, dim3(grid), dim3(64), 0, s, B, p); break;
+    case S_CG_BETA: hipLaunchKernelGGL(scalar_kernel<S_CG_BETA>, dim3(grid), dim3(64), 0, s, B, p); break;
+    default: hipLaunchKernelGGL(scalar_kernel<S_SUM>, dim3(grid), dim3(64), 0, s, B, p); break;
     }
 }
 
-void k_copy(int prec_dst, Field dst, int prec_src, Field src, int64_t Vh, int nrhs, const int *mask, hipStream_t s)
+void vec_launch(int op, int prec, const std::vector<VSeg> &segs, hipStream_t s)
 {
-    ProfScope ps(PROF_BLAS, vec_bytes(prec_dst, Vh, nrhs, 1) + vec_bytes(prec_src, Vh, nrhs, 1), s);
+    static const int nvec[] = {4, 3, 7, 6, 3, 1, 1, 2};
+    ProfScope ps(PROF_BLAS, vec_bytes(prec, segs, nvec[op]), s);
+    Segs<VSeg> B = make_segs(segs, vec_items);
+    const int grid = grid_for(B.prefix[B.n], PERSIST);
+    switch (op) {
+    case V_BICG_P: vec_dispatch<V_BICG_P>(prec, B, grid, s); break;
+    case V_BICG_S: vec_dispatch<V_BICG_S>(prec, B, grid, s); break;
+    case V_BICG_XR: vec_dispatch<V_BICG_XR>(prec, B, grid, s); break;
+    case V_CG_XR: vec_dispatch<V_CG_XR>(prec, B, grid, s); break;
+    case V_CG_P: vec_dispatch<V_CG_P>(prec, B, grid, s); break;
+    case V_ZERO: vec_dispatch<V_ZERO>(prec, B, grid, s); break;
+    case V_NORM2: vec_dispatch<V_NORM2>(prec, B, grid, s); break;
+    default: vec_dispatch<V_DOT>(prec, B, grid, s); break;
+    }
+}
+
+void copy_launch(int prec_dst, int prec_src, const std::vector<VSeg> &segs, hipStream_t s)
+{
+    ProfScope ps(PROF_BLAS, vec_bytes(prec_dst, segs, 1) + vec_bytes(prec_src, segs, 1), s);
+    Segs<VSeg> B = make_segs(segs, vec_items);
+    const int grid = grid_for(B.prefix[B.n], PERSIST);
     switch (prec_dst) {
-    case P64: copy_from<double>(prec_src, dst, src, mask, Vh, nrhs, s); break;
-    case P32: copy_from<float>(prec_src, dst, src, mask, Vh, nrhs, s); break;
-    case P16: copy_from<__half>(prec_src, dst, src, mask, Vh, nrhs, s); break;
-    default: copy_from<__hip_bfloat16>(prec_src, dst, src, mask, Vh, nrhs, s); break;
+    case P64: copy_from<double>(prec_src, B, grid, s); break;
+    case P32: copy_from<float>(prec_src, B, grid, s); break;
+    case P16: copy_from<__half>(prec_src, B, grid, s); break;
+    default: copy_from<__hip_bfloat16>(prec_src, B, grid, s); break;
     }
 }
 
-void k_zero(int prec, Field f, int64_t Vh, int nrhs, const int *mask, hipStream_t s)
+void fold_launch(int prec, const std::vector<VSeg> &segs, hipStream_t s)
 {
-    ProfScope ps(PROF_BLAS, vec_bytes(prec, Vh, nrhs, 1), s);
-    DL_DISPATCH(prec, zero_kernel, vgrid(Vh, nrhs), dim3(BS), 0, s, f, mask, Vh);
+    ProfScope ps(PROF_BLAS, vec_bytes(P64, segs, 2) + vec_bytes(prec, segs, 2), s);
+    Segs<VSeg> B = make_segs(segs, vec_items);
+    const int grid = grid_for(B.prefix[B.n], PERSIST);
+    switch (prec) {
+    case P64: hipLaunchKernelGGL(fold_kernel<double>, dim3(grid), dim3(BS), 0, s, B); break;
+    case P32: hipLaunchKernelGGL(fold_kernel<float>, dim3(grid), dim3(BS), 0, s, B); break;
+    case P16: hipLaunchKernelGGL(fold_kernel<__half>, dim3(grid), dim3(BS), 0, s, B); break;
+    default: hipLaunchKernelGGL(fold_kernel<__hip_bfloat16>, dim3(grid), dim3(BS), 0, s, B); break;
+    }
 }
 
-void k_fold_x(Field x64, int prec, Field xlo, int64_t Vh, int nrhs, const int *mask, hipStream_t s)
+void sub_launch(const std::vector<VSeg> &segs, hipStream_t s)
 {
-    ProfScope ps(PROF_BLAS, vec_bytes(P64, Vh, nrhs, 2) + vec_bytes(prec, Vh, nrhs, 2), s);
-    DL_DISPATCH(prec, fold_kernel, vgrid(Vh, nrhs), dim3(BS), 0, s, x64, xlo, mask, Vh);
-}
-
-void k_norm2_parts(int prec, Field f, int64_t Vh, int nrhs, const int *mask, double *parts, hipStream_t s)
-{
-    ProfScope ps(PROF_BLAS, vec_bytes(prec, Vh, nrhs, 1), s);
-    DL_DISPATCH(prec, norm2_kernel, vgrid(Vh, nrhs), dim3(BS), 0, s, f, mask, Vh, parts);
-}
-
-void k_dot_parts(int prec, Field a, Field b, int64_t Vh, int nrhs, const int *mask, double *parts, hipStream_t s)
-{
-    ProfScope ps(PROF_BLAS, vec_bytes(prec, Vh, nrhs, 2), s);
-    DL_DISPATCH(prec, dot_kernel, vgrid(Vh, nrhs), dim3(BS), 0, s, a, b, mask, Vh, parts);
-}
-
-void k_sub(Field dst, Field a, Field b, int64_t Vh, int nrhs, const int *mask, hipStream_t s)
-{
-    ProfScope ps(PROF_BLAS, vec_bytes(P64, Vh, nrhs, 3), s);
-    hipLaunchKernelGGL(sub_kernel, vgrid(Vh, nrhs), dim3(BS), 0, s, dst, a, b, mask, Vh);
+    ProfScope ps(PROF_BLAS, vec_bytes(P64, segs, 3), s);
+    Segs<VSeg> B = make_segs(segs, vec_items);
+    hipLaunchKernelGGL(sub_kernel, dim3(grid_for(B.prefix[B.n], PERSIST)), dim3(BS), 0, s, B);
 }
 
 }  // namespace dl

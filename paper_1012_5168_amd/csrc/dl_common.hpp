@@ -245,17 +245,39 @@ __device__ __forceinline__ void block_sum(double v[N], double *scratch)
     }
 }
 
-// ---------------------------------------------------------------- block order
+// ---------------------------------------------------------------- work distribution
 
-// The hardware hands consecutive workgroups to the 8 XCDs in turn.  Remap so
-// that each XCD works through a contiguous range of logical blocks: the
-// neighbour sites a block gathers then sit in the same XCD's L2.
-__device__ __forceinline__ int xcd_remap(int b, int nblocks)
+// A launch covers up to MAXSEG segments (lattices of a batch, each with its
+// own operands); prefix[s] is the first work item of segment s and
+// prefix[n] the total.
+constexpr int MAXSEG = 4;
+template <typename A>
+struct Segs {
+    int n;
+    int prefix[MAXSEG + 1];
+    A a[MAXSEG];
+};
+
+// Visit the work items of this block.  The hardware hands consecutive
+// workgroups to the 8 XCDs in turn; items are dealt out so that the blocks of
+// one XCD walk one contiguous chunk of the item range, which keeps the
+// neighbour sites a block gathers in that XCD's L2.  The grid is either one
+// block per item or a multiple of 8 blocks (persistent: each block loops).
+template <typename A, typename F>
+__device__ __forceinline__ void for_each_item(const Segs<A> &B, F &&f)
 {
-    const int nx = 8;
-    int q = nblocks / nx, rem = nblocks % nx;
-    int xcd = b % nx, j = b / nx;
-    return xcd * q + min(xcd, rem) + j;
+    const int total = B.prefix[B.n];
+    const int nx = 8, P = gridDim.x;
+    const int xcd = blockIdx.x % nx, j = blockIdx.x / nx;
+    const int nbx = P / nx + (xcd < P % nx ? 1 : 0);
+    const int q = total / nx, rem = total % nx;
+    const int start = xcd * q + min(xcd, rem), cnt = q + (xcd < rem ? 1 : 0);
+    for (int i = j; i < cnt; i += nbx) {
+        const int item = start + i;
+        int s = 0;
+        while (s + 1 < B.n && item >= B.prefix[s + 1]) ++s;
+        f(B.a[s], item - B.prefix[s]);
+    }
 }
 
 }  // namespace dl

@@ -127,15 +127,14 @@ constexpr int nparts_c()
     return EPI == EPI_XPAY_DOT ? 2 : EPI == EPI_XPAY_TS ? 3 : (EPI == EPI_XPAY_NRM || EPI == EPI_XMY_NRM) ? 1 : 0;
 }
 
+// One work item: site block sb of right-hand-side group grp, item L = grp * nblk + sb.
 template <typename S, int NE, bool DAG, int EPI, int NR>
-__global__ __launch_bounds__(256) void dslash_kernel(DKArgs a)
+__device__ __forceinline__ void dslash_item(const DKArgs &a, int L, double *red)
 {
     using R = typename Fmt<S>::R;
     constexpr int NP = nparts_c<EPI>();
-    __shared__ double red[(NP > 0 ? NP : 1) * 4];
 
     const Geom &g = a.g;
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
     const int grp = L / a.nblk, sb = L - grp * a.nblk;
     int rhs[NR];
     bool live[NR];
@@ -264,7 +263,16 @@ __global__ __launch_bounds__(256) void dslash_kernel(DKArgs a)
     }
 }
 
+// A launch covers the work items of every segment (lattice) of the batch.
+template <typename S, int NE, bool DAG, int EPI, int NR>
+__global__ __launch_bounds__(256) void dslash_kernel(Segs<DKArgs> B)
+{
+    constexpr int NP = nparts_c<EPI>();
+    __shared__ double red[(NP > 0 ? NP : 1) * 4];
+    for_each_item(B, [&](const DKArgs &a, int L) { dslash_item<S, NE, DAG, EPI, NR>(a, L, red); });
+}
+
 template <typename S>
-void launch_dslash_t(const DslashCall &c, int nr, int bs, hipStream_t s);
+void launch_dslash_t(const DslashCall *c, int nseg, int nr, int bs, int persistent, hipStream_t s);
 
 }  // namespace dl

@@ -106,6 +106,10 @@ enum ProfKind { PROF_DSLASH = 0, PROF_BLAS = 1, PROF_TRACE = 2, PROF_DSLASH_PLAI
 // work ran) plus unit_bytes times the number of units the kernel counted
 // into *counter divided by `units_div` (the hopping kernel counts live
 // right-hand-side blocks, so masked-off right-hand sides move no bytes).
+struct ProfPart {
+    unsigned *counter;
+    double unit_bytes, fixed_bytes, units_div;
+};
 struct ProfScope {
     ProfScope(int kind, double bytes, hipStream_t s, int kind2 = -1);
     ~ProfScope();
@@ -113,8 +117,7 @@ struct ProfScope {
     double bytes;
     hipStream_t s;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    unsigned *counter = nullptr;
-    double unit_bytes = 0, fixed_bytes = 0, units_div = 1;
+    std::vector<ProfPart> parts;  // counted byte terms (replace `bytes` when present)
 };
 // a zeroed device counter for the next profiled launch (null when profiling is off)
 unsigned *prof_counter();
@@ -159,16 +162,19 @@ struct DslashCall {
 };
 
 // launch with the tuned (or default) configuration; returns the number of
-// site blocks per right-hand side (the partials' middle extent)
+// site blocks per right-hand side (the partials' middle extent) of each call.
+// A batch of calls (same precision, link format, adjoint flag and epilogue;
+// one per lattice) runs as one launch.
 int launch_dslash(const DslashCall &c, hipStream_t s);
+std::vector<int> launch_dslash_batch(const std::vector<DslashCall> &calls, hipStream_t s);
 
-// launch configuration of the hopping kernel: right-hand sides per thread and
-// sites per workgroup
+// launch configuration of the hopping kernel: right-hand sides per thread,
+// sites per workgroup and the persistent grid cap (0 = one block per item)
 struct TuneChoice {
-    int nr, bs;
+    int nr, bs, persistent;
 };
-TuneChoice tune_lookup(const DslashCall &c, hipStream_t s);
-void launch_dslash_any(const DslashCall &c, int nr, int bs, hipStream_t s);
+TuneChoice tune_lookup(const std::vector<DslashCall> &c, hipStream_t s);
+void launch_dslash_any(const std::vector<DslashCall> &c, int nr, int bs, int persistent, hipStream_t s);
 int dslash_site_blocks(const Geom &g, int prec, int nrhs);
 
 // ---------------------------------------------------------------- Krylov vector kernels
@@ -194,41 +200,47 @@ struct KState {
 
 int blas_blocks(int64_t Vh);
 
-// BiCGStab scalar updates (one wave per right-hand side)
-void k_bicg_init(KState *st, int *act, int *upd, int nrhs, const double *b2_parts_e, const double *b2_parts_o,
-                 int nblk, double tol2, double delta2, int maxiter, hipStream_t s);
-// rho_new from partials (rhat, r) [, |r|^2]; first = 1 restarts the recursion for
-// right-hand sides selected by mask (null = all); mixed enables reliable-update triggers
-void k_bicg_rho(KState *st, int *act, int *upd, const int *mask, int nrhs, const double *parts, int nblk, int np,
-                int first, int mixed, hipStream_t s);
-void k_bicg_alpha(KState *st, const int *act, int nrhs, const double *parts, int nblk, hipStream_t s);
-void k_bicg_omega(KState *st, const int *act, int nrhs, const double *parts, int nblk, hipStream_t s);
-// after an FP64 residual recomputation for the right-hand sides flagged in upd
-void k_true_residual(KState *st, int *act, int *upd, int *restart, int nrhs, const double *parts_e,
-                     const double *parts_o, int nblk, int final_check, hipStream_t s);
-// CGNR scalar updates
-void k_cg_init(KState *st, int *act, int nrhs, const double *parts, int nblk, int iters, hipStream_t s);
-void k_cg_alpha(KState *st, int *act, int nrhs, const double *parts, int nblk, hipStream_t s);
-void k_cg_beta(KState *st, int *act, int nrhs, const double *parts, int nblk, hipStream_t s);
-void k_sum_parts(const double *parts, int nrhs, int nblk, int nparts, double *out, hipStream_t s);
+// Operands of a Krylov vector kernel for one segment (lattice).
+struct VSeg {
+    Field f[5];
+    const KState *st = nullptr;
+    const int *mask = nullptr;  // per right-hand side flags selecting who acts (null = all)
+    int64_t Vh = 0;
+    int nrhs = 0;
+    double *parts = nullptr;    // [nrhs][blas_blocks(Vh)][np] for the reducing operations
+};
+enum VOp { V_BICG_P = 0, V_BICG_S, V_BICG_XR, V_CG_XR, V_CG_P, V_ZERO, V_NORM2, V_DOT };
+void vec_launch(int op, int prec, const std::vector<VSeg> &segs, hipStream_t s);
+void copy_launch(int prec_dst, int prec_src, const std::vector<VSeg> &segs, hipStream_t s);  // f0 = f1
+void fold_launch(int prec, const std::vector<VSeg> &segs, hipStream_t s);   // f0 (FP64) += f1; f1 = 0
+void sub_launch(const std::vector<VSeg> &segs, hipStream_t s);              // f0 = f1 - f2 (FP64)
 
-// vector kernels (fields in storage precision `prec`; masked by act)
-void k_bicg_p(int prec, Field p, Field r, Field v, const KState *st, const int *act, int64_t Vh, int nrhs,
-              hipStream_t s);
-void k_bicg_s(int prec, Field r, Field v, const KState *st, const int *act, int64_t Vh, int nrhs, hipStream_t s);
-void k_bicg_xr(int prec, Field x, Field r, Field p, Field t, Field rh, const KState *st, const int *act, int64_t Vh,
-               int nrhs, double *parts, hipStream_t s);
-void k_cg_xr(int prec, Field x, Field r, Field p, Field q, const KState *st, const int *act, int64_t Vh, int nrhs,
-             double *parts, hipStream_t s);
-void k_cg_p(int prec, Field p, Field r, const KState *st, const int *act, int64_t Vh, int nrhs, hipStream_t s);
-
-// generic field kernels (mask: per right-hand side flags selecting who acts; null = all)
-void k_copy(int prec_dst, Field dst, int prec_src, Field src, int64_t Vh, int nrhs, const int *mask, hipStream_t s);
-void k_zero(int prec, Field f, int64_t Vh, int nrhs, const int *mask, hipStream_t s);
-void k_fold_x(Field x64, int prec, Field xlo, int64_t Vh, int nrhs, const int *mask, hipStream_t s);
-void k_norm2_parts(int prec, Field f, int64_t Vh, int nrhs, const int *mask, double *parts, hipStream_t s);
-void k_dot_parts(int prec, Field a, Field b, int64_t Vh, int nrhs, const int *mask, double *parts, hipStream_t s);
-void k_sub(Field dst, Field a, Field b, int64_t Vh, int nrhs, const int *mask, hipStream_t s);
+// Operands of a per-right-hand-side scalar kernel for one segment.
+struct SSeg {
+    KState *st = nullptr;
+    int *act = nullptr, *upd = nullptr, *restart = nullptr;
+    const int *mask = nullptr;
+    const double *parts = nullptr, *parts2 = nullptr;
+    int nblk = 0;   // site blocks of the producing kernel (partials' middle extent)
+    int nrhs = 0;
+    double *out = nullptr;
+};
+struct SParams {
+    double tol2 = 0, delta2 = 0;
+    int maxiter = 0, np = 0, first = 0, mixed = 0, final_check = 0;
+};
+enum SOp {
+    S_BICG_INIT = 0,  // parts (+ parts2): |b_e|^2 (+ |b_o|^2)
+    S_BICG_RHO,       // parts: (rhat, r) [, |r|^2]
+    S_BICG_ALPHA,     // parts: (rhat, v)
+    S_BICG_OMEGA,     // parts: (t, s), |t|^2
+    S_TRUE_RES,       // parts (+ parts2): FP64 residual norms
+    S_CG_INIT,        // parts: |r|^2
+    S_CG_ALPHA,       // parts: (p, q)
+    S_CG_BETA,        // parts: |r|^2
+    S_SUM             // out[rhs * np + k] = sum of partials
+};
+void scalar_launch(int op, const std::vector<SSeg> &segs, const SParams &p, hipStream_t s);
 
 // ---------------------------------------------------------------- fields, sources, traces
 

@@ -1,12 +1,14 @@
 // dl_tune.cpp -- autotuner for the hopping kernel's launch configuration.
 //
 // The tunables are the number of right-hand sides a thread carries (1 or 2:
-// links loaded once serve both) and the workgroup size (64, 128 or 256
-// sites).  The first time a (precision, link format, adjoint, epilogue,
-// right-hand sides, lattice) combination is launched, each candidate is timed
+// links loaded once serve both), the workgroup size (64, 128 or 256 sites)
+// and whether the grid is persistent (a capped number of workgroups looping
+// over the work items).  The first time a (precision, link format, adjoint,
+// epilogue, right-hand sides, lattices) combination is launched, each
+// candidate is timed
 // with HIP events on the real operands (every hopping launch is idempotent:
 // its output never aliases an input) and the fastest is kept, in memory and
-// in a text cache file (DL_TUNE_CACHE, default ~/.cache/dloops/tune_gfx950.txt).
+// in a text cache file (DL_TUNE_CACHE, default ~/.cache/dloops/tune_gfx950_v2.txt).
 // DL_TUNE=0 disables tuning and uses 1 right-hand side per thread with 256
 // sites per workgroup.  Tuning never runs while the stream is being captured.
 #include <hip/hip_runtime.h>
@@ -26,21 +28,31 @@ namespace dl {
 namespace {
 
 using Key = std::tuple<int, int, int, int, int, int, int, int, int>;
+const int PERSIST_GRID = 8 * 32 * 8;  // 8 workgroups per CU on 256 CUs
 
 std::mutex g_mu;
 std::map<Key, TuneChoice> g_cache;
 bool g_loaded = false;
 
-Key make_key(const DslashCall &c)
+// the lattice part of the key folds every segment's shape into one number
+Key make_key(const std::vector<DslashCall> &cs)
 {
-    return Key{c.prec, c.recon, c.dag ? 1 : 0, c.epi, c.nrhs, c.g.X, c.g.Y, c.g.Z, c.g.T};
+    const DslashCall &c = cs[0];
+    int nrhs = 0;
+    long long shape = 0;
+    for (const DslashCall &d : cs) {
+        nrhs += d.nrhs;
+        shape = shape * 1000003LL + ((((long long)d.g.X * 131 + d.g.Y) * 131 + d.g.Z) * 131 + d.g.T) * 7 + d.nrhs;
+    }
+    const int h1 = (int)(shape & 0x3fffffff), h2 = (int)((shape >> 30) & 0x3fffffff);
+    return Key{c.prec, c.recon, c.dag ? 1 : 0, c.epi, nrhs, (int)cs.size(), h1, h2, c.g.T};
 }
 
 std::string cache_path()
 {
     if (const char *p = std::getenv("DL_TUNE_CACHE")) return p;
     const char *home = std::getenv("HOME");
-    return std::string(home ? home : "/tmp") + "/.cache/dloops/tune_gfx950.txt";
+    return std::string(home ? home : "/tmp") + "/.cache/dloops/tune_gfx950_v2.txt";
 }
 
 bool tuning_enabled()
@@ -55,11 +67,12 @@ void load_locked()
     g_loaded = true;
     FILE *f = std::fopen(cache_path().c_str(), "r");
     if (!f) return;
-    int v[11];
-    while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6], &v[7],
-                       &v[8], &v[9], &v[10]) == 11) {
-        if ((v[9] == 1 || v[9] == 2) && (v[10] == 64 || v[10] == 128 || v[10] == 256))
-            g_cache[Key{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8]}] = TuneChoice{v[9], v[10]};
+    int v[12];
+    while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6],
+                       &v[7], &v[8], &v[9], &v[10], &v[11]) == 12) {
+        if ((v[9] == 1 || v[9] == 2) && (v[10] == 64 || v[10] == 128 || v[10] == 256) &&
+            (v[11] == 0 || v[11] == PERSIST_GRID))
+            g_cache[Key{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8]}] = TuneChoice{v[9], v[10], v[11]};
     }
     std::fclose(f);
 }
@@ -72,30 +85,33 @@ void save_locked(const Key &k, const TuneChoice &t)
         if (i == dir.size() || dir[i] == '/') mkdir(dir.substr(0, i).c_str(), 0755);
     FILE *f = std::fopen(path.c_str(), "a");
     if (!f) return;
-    std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+    std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
                  std::get<3>(k), std::get<4>(k), std::get<5>(k), std::get<6>(k), std::get<7>(k), std::get<8>(k), t.nr,
-                 t.bs);
+                 t.bs, t.persistent);
     std::fclose(f);
 }
 
-bool aliases(const DslashCall &c)
+bool aliases(const std::vector<DslashCall> &cs)
 {
-    return c.out.d == c.in.d || (c.x.d && c.out.d == c.x.d) || (c.y.d && c.out.d == c.y.d);
+    for (const DslashCall &c : cs)
+        if (c.out.d == c.in.d || (c.x.d && c.out.d == c.x.d) || (c.y.d && c.out.d == c.y.d)) return true;
+    return false;
 }
 
 }  // namespace
 
-TuneChoice tune_lookup(const DslashCall &c, hipStream_t s)
+TuneChoice tune_lookup(const std::vector<DslashCall> &c, hipStream_t s)
 {
-    const TuneChoice dflt{1, 256};
+    const TuneChoice dflt{1, 256, 0};
     if (!tuning_enabled() || aliases(c)) return dflt;
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return dflt;
     const Key k = make_key(c);
     std::lock_guard<std::mutex> lk(g_mu);
     load_locked();
     auto it = g_cache.find(k);
     if (it != g_cache.end()) return it->second;
+    // no timing while a graph is being captured
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return dflt;
 
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return dflt;
@@ -106,26 +122,28 @@ TuneChoice tune_lookup(const DslashCall &c, hipStream_t s)
     // repeat until each measurement spans at least ~1 ms of kernel time
     TuneChoice best = dflt;
     float best_ms = 1e30f;
-    DslashCall t = c;
-    t.live_count = nullptr;
+    std::vector<DslashCall> t = c;
+    for (DslashCall &d : t) d.live_count = nullptr;
     for (int nr : {1, 2}) {
         for (int bs : {64, 128, 256}) {
-            launch_dslash_any(t, nr, bs, s);  // warm
-            int reps = 1;
-            float ms = 0;
-            for (int attempt = 0; attempt < 3; ++attempt) {
-                (void)hipEventRecord(e0, s);
-                for (int r = 0; r < reps; ++r) launch_dslash_any(t, nr, bs, s);
-                (void)hipEventRecord(e1, s);
-                (void)hipEventSynchronize(e1);
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                if (ms > 1.0f || reps >= 64) break;
-                reps *= 8;
-            }
-            const float per = ms / reps;
-            if (hipGetLastError() == hipSuccess && per < best_ms) {
-                best_ms = per;
-                best = TuneChoice{nr, bs};
+            for (int pg : {0, PERSIST_GRID}) {
+                launch_dslash_any(t, nr, bs, pg, s);  // warm
+                int reps = 1;
+                float ms = 0;
+                for (int attempt = 0; attempt < 3; ++attempt) {
+                    (void)hipEventRecord(e0, s);
+                    for (int r = 0; r < reps; ++r) launch_dslash_any(t, nr, bs, pg, s);
+                    (void)hipEventRecord(e1, s);
+                    (void)hipEventSynchronize(e1);
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    if (ms > 1.0f || reps >= 64) break;
+                    reps *= 8;
+                }
+                const float per = ms / reps;
+                if (hipGetLastError() == hipSuccess && per < best_ms) {
+                    best_ms = per;
+                    best = TuneChoice{nr, bs, pg};
+                }
             }
         }
     }
