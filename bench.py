@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--noises", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tsm", action="store_true", help="skip the truncated-solver-method comparison")
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="first run a plain device copy (2 GiB read, 2 GiB written), the reference for hardware byte counters")
     ap.add_argument("--cpu-only", action="store_true", help="time only the CPU oracle sample")
     return ap.parse_args()
 
@@ -77,6 +80,48 @@ def cpu_baseline(w):
     }
 
 
+def tsm_comparison(dl, G, w, L_plain, ms_plain):
+    """Time per loop at fixed statistical error: the truncated solver method (400 low-precision
+    truncated solves in FP16 storage / FP32 arithmetic, 25 CGNR iterations, plus 16 high-precision
+    corrections in FP32 with FP64 reliable updates to 1e-10, undiluted noises) against the plain
+    FP64 estimate of the timed step (24 spin-colour-diluted noises), on the same field.
+    time_to_equal_variance = T_tsm * Var_tsm / Var_plain, per Gamma, averaged over t."""
+    import numpy as np
+    import torch
+
+    t = synth_workload("tsm_16x16x16x32")
+    gam = [0, 15]
+    n_lp, n_hp = 400, 16
+    lpp = dl.solve_params(solver=dl.DL_CGNR, prec=dl.DL_F16, fixed_iters=25)
+    hpp = dl.solve_params(prec=dl.DL_F32, tol=1e-10, maxiter=1000)
+    src = dl.z2_sources(t["noise_seed"], n_lp + n_hp)
+    dl.loops_tsm(G, t["kappa"], dl.z2_sources(t["noise_seed"] + 7, 3), 2, 1, gam, lpp, hpp)  # warm / tune
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a, b, c, st = dl.loops_tsm(G, t["kappa"], src, n_lp, n_hp, gam, lpp, hpp)
+    torch.cuda.synchronize()
+    ms_tsm = (time.perf_counter() - t0) * 1e3
+    est, var_t = dl.tsm_estimate(a, b, c)
+    var_p = np.var(L_plain, axis=0, ddof=1) / len(L_plain)
+    out = {"ms_tsm": round(ms_tsm, 2), "ms_plain": round(ms_plain, 2), "n_lp": n_lp, "n_hp": n_hp,
+           "hp_converged": all(x[0] == dl.DL_OK for x in st[(n_lp + n_hp):])}
+    for k, g in enumerate(gam):
+        vt = float(np.mean(var_t[k].real))
+        vp = float(np.mean(var_p[k].real))
+        out["gamma%d" % g] = {
+            "var_tsm": vt, "var_plain": vp,
+            "time_to_equal_variance_ms": round(ms_tsm * vt / vp, 2),
+            "ratio_vs_plain": round(ms_tsm * vt / (vp * ms_plain), 4),
+        }
+    return out
+
+
+def synth_workload(name):
+    import synth
+
+    return synth.WORKLOADS[name]
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -102,7 +147,7 @@ def main():
     dims, kappa = w["dims"], w["kappa"]
     U = synth.gauge_field(dims, w["eps"], w["gauge_seed"])
     lat = dl.Lattice(dims, 1)
-    G = dl.Gauge(lat, U, precs=(dl.DL_F64,), recon=12)
+    G = dl.Gauge(lat, U, precs=(dl.DL_F64, dl.DL_F32, dl.DL_F16), recon=12)
     stream = torch.cuda.current_stream()
     prm = dl.solve_params(tol=1e-10, maxiter=1000)
     gam = [0, 15]
@@ -111,6 +156,15 @@ def main():
 
     def step():
         return dl.loops(G, kappa, src, gam, prm)
+
+    if args.copy_reference:
+        n = 1 << 28  # 2^28 doubles: 2 GiB read once and written once
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print("copy reference: %d bytes read, %d bytes written" % (8 * n, 8 * n), file=sys.stderr, flush=True)
+        del a, b
 
     for _ in range(args.warmup):
         L, st = step()
@@ -176,6 +230,8 @@ def main():
             "algorithmic_bytes_per_launch": round(by_p / max(n_p, 1)),
         },
     }
+    if not args.no_tsm:
+        out["tsm"] = tsm_comparison(dl, G, w, L, ms_step)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
