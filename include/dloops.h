@@ -286,6 +286,19 @@ int dl_sources_fill(dl_lattice lat, const dl_sources *src, int64_t first_rhs, in
 int dl_profile_enable(int32_t on);
 int64_t dl_profile_read(int32_t kind, double *ms, double *bytes);
 
+/*
+ * Launch configuration of the most recent profiled hopping launch of profile
+ * kind 0 (any hopping launch) or 3 (the plain one), as chosen by the
+ * autotuner: cfg[0] = kernel (0 = item kernel, one thread per site and
+ * cfg[1] right-hand sides; 1 = LDS-link kernel, links of a 64-site block in
+ * LDS and cfg[1] wavefronts walking the right-hand sides), cfg[2] = sites per
+ * workgroup, cfg[3] = persistent grid cap (item kernel, 0 = none) or region
+ * size in site blocks (LDS-link kernel).  cfg (host, 4 int32) is all -1 when
+ * no such launch was profiled since dl_profile_enable(1).  Returns DL_EINVAL
+ * for another kind or a null cfg.
+ */
+int dl_profile_config(int32_t kind, int32_t *cfg);
+
 #ifdef __cplusplus
 }
 #endif

@@ -115,6 +115,7 @@ _SIGNATURES = {
     "dl_sources_count": (ctypes.c_int64, [_P, ctypes.POINTER(dl_sources)]),
     "dl_sources_fill": (ctypes.c_int, [_P, ctypes.POINTER(dl_sources), ctypes.c_int64, ctypes.c_int64, _P, _P]),
     "dl_profile_enable": (ctypes.c_int, [ctypes.c_int32]),
+    "dl_profile_config": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "dl_profile_read": (ctypes.c_int64, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double)]),
 }
@@ -272,6 +273,14 @@ def dl_sources_fill(lat, sources, first_rhs, nrhs, out, stream=None):
 
 def dl_profile_enable(on: bool = True):
     load().dl_profile_enable(1 if on else 0)
+
+
+def dl_profile_config(kind: int):
+    """(kernel, right-hand sides or wavefronts, sites per workgroup, grid cap or region blocks) of the
+    last profiled hopping launch of that kind; all -1 if none."""
+    cfg = (ctypes.c_int32 * 4)()
+    _check(load().dl_profile_config(int(kind), cfg))
+    return tuple(int(v) for v in cfg)
 
 
 def dl_profile_read(kind: int):

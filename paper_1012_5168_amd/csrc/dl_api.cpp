@@ -104,6 +104,8 @@ static std::vector<ProfRec> g_prof_pending;
 static double g_prof_ms[PROF_NKIND], g_prof_bytes[PROF_NKIND];
 static int64_t g_prof_n[PROF_NKIND];
 static DevBuf g_prof_ctr;  // device counters, one per profiled hopping launch and lattice
+static TuneChoice g_prof_cfg[PROF_NKIND];  // last profiled hopping configuration per kind
+static bool g_prof_cfg_set[PROF_NKIND];
 static int g_prof_next = 0;
 static const int PROF_SLOTS = 1 << 16;
 
@@ -197,7 +199,7 @@ static void prof_drain()
 int dslash_site_blocks(const Geom &g, int /*prec*/, int /*nrhs*/) { return (g.Vh + 63) / 64; }
 
 template <typename S>
-void launch_dslash_t(const DslashCall *c, int nseg, int nr, int bs, int persistent, hipStream_t s);
+void launch_dslash_t(const DslashCall *c, int nseg, int kind, int nr, int bs, int persistent, hipStream_t s);
 
 // algorithmic bytes of one launch: every operand moved once.  Per live
 // right-hand side: the input half spinor, the output and the epilogue
@@ -213,13 +215,24 @@ static void dslash_bytes(const DslashCall &c, double &per_rhs, double &links)
     per_rhs = nfield * field;
 }
 
-void launch_dslash_any(const std::vector<DslashCall> &c, int nr, int bs, int persistent, hipStream_t s)
+bool dslash_lds_ok(int prec, int recon)
 {
+    return 8.0 * (recon == 12 ? 6 : 9) * 64 * (double)elem_bytes(prec) <= 65536.0;
+}
+
+int dslash_block_sites(const DslashCall &c, const TuneChoice &t)
+{
+    return (t.kind == 1 && dslash_lds_ok(c.prec, c.recon)) ? 64 : t.bs;
+}
+
+void launch_dslash_any(const std::vector<DslashCall> &c, const TuneChoice &t, hipStream_t s)
+{
+    const int n = (int)c.size();
     switch (c[0].prec) {
-    case P64: launch_dslash_t<double>(c.data(), (int)c.size(), nr, bs, persistent, s); break;
-    case P32: launch_dslash_t<float>(c.data(), (int)c.size(), nr, bs, persistent, s); break;
-    case P16: launch_dslash_t<__half>(c.data(), (int)c.size(), nr, bs, persistent, s); break;
-    default: launch_dslash_t<__hip_bfloat16>(c.data(), (int)c.size(), nr, bs, persistent, s); break;
+    case P64: launch_dslash_t<double>(c.data(), n, t.kind, t.nr, t.bs, t.persistent, s); break;
+    case P32: launch_dslash_t<float>(c.data(), n, t.kind, t.nr, t.bs, t.persistent, s); break;
+    case P16: launch_dslash_t<__half>(c.data(), n, t.kind, t.nr, t.bs, t.persistent, s); break;
+    default: launch_dslash_t<__hip_bfloat16>(c.data(), n, t.kind, t.nr, t.bs, t.persistent, s); break;
     }
 }
 
@@ -235,13 +248,24 @@ std::vector<int> launch_dslash_batch(const std::vector<DslashCall> &c0, hipStrea
     for (size_t k = 0; k < c.size(); ++k) {
         double per_rhs, links;
         dslash_bytes(c[k], per_rhs, links);
-        nblk[k] = (c[k].g.Vh + t.bs - 1) / t.bs;
+        nblk[k] = (c[k].g.Vh + dslash_block_sites(c[k], t) - 1) / dslash_block_sites(c[k], t);
         nominal += per_rhs * c[k].nrhs + links;
         c[k].live_count = counted ? prof_counter() : nullptr;
         ps.parts.push_back({c[k].live_count, per_rhs, links, (double)nblk[k]});
     }
     ps.bytes = nominal;
-    launch_dslash_any(c, t.nr, t.bs, t.persistent, s);
+    if (counted) {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        TuneChoice used = t;
+        if (t.kind == 1 && !dslash_lds_ok(c[0].prec, c[0].recon)) used = TuneChoice{0, 1, 256, 0};
+        if (used.kind == 1) used.bs = 64;
+        for (int k : {ps.kind, ps.kind2})
+            if (k >= 0 && k < PROF_NKIND) {
+                g_prof_cfg[k] = used;
+                g_prof_cfg_set[k] = true;
+            }
+    }
+    launch_dslash_any(c, t, s);
     return nblk;
 }
 
@@ -1556,6 +1580,7 @@ extern "C" int dl_profile_enable(int32_t on)
         g_prof_ms[k] = 0;
         g_prof_bytes[k] = 0;
         g_prof_n[k] = 0;
+        g_prof_cfg_set[k] = false;
     }
     if (on) {
         try {
@@ -1568,6 +1593,22 @@ extern "C" int dl_profile_enable(int32_t on)
         }
         g_prof_next = 0;
         g_prof_on = true;
+    }
+    return DL_OK;
+}
+
+extern "C" int dl_profile_config(int32_t kind, int32_t *cfg)
+{
+    if ((kind != PROF_DSLASH && kind != PROF_DSLASH_PLAIN) || cfg == nullptr) return DL_EINVAL;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_cfg_set[kind]) {
+        for (int i = 0; i < 4; ++i) cfg[i] = -1;
+    } else {
+        const TuneChoice &t = g_prof_cfg[kind];
+        cfg[0] = t.kind;
+        cfg[1] = t.nr;
+        cfg[2] = t.bs;
+        cfg[3] = t.persistent;
     }
     return DL_OK;
 }

@@ -75,8 +75,47 @@ __device__ __forceinline__ void reconstruct(cx<R> acc[12], const cx<R> g[6])
     }
 }
 
-// one hop: neighbour spinor at checkerboard index nb (other parity), link at
-// (lpar, lcb); forward hops multiply by U, backward hops by U^+
+// One hop on a loaded neighbour spinor: project, colour-multiply by U
+// (forward) or U^+ (backward), reconstruct into the accumulator.
+template <typename R, int MU, int SG, bool FWD>
+__device__ __forceinline__ void hop_mul(const cx<R> u[9], const cx<R> psi[12], R bsign, cx<R> acc[12])
+{
+    cx<R> h[6];
+    project<R, MU, SG>(psi, h);
+    if constexpr (MU == 3) {
+#pragma unroll
+        for (int e = 0; e < 6; ++e) h[e] = bsign * h[e];
+    }
+    cx<R> gg[6];
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            cx<R> t = {R(0), R(0)};
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                if constexpr (FWD)
+                    cmac(t, u[3 * i + j], h[3 * sp + j]);
+                else
+                    cmac_conj(t, u[3 * j + i], h[3 * sp + j]);
+            }
+            gg[3 * sp + i] = t;
+        }
+    reconstruct<R, MU, SG>(acc, gg);
+}
+
+// Pin the accumulators: this forces a hop's arithmetic to finish before the
+// next hop's loads issue.  Without it the compiler issues all eight
+// neighbours' loads first and runs out of registers.
+template <typename R>
+__device__ __forceinline__ void pin_acc(cx<R> acc[12])
+{
+#pragma unroll
+    for (int e = 0; e < 12; ++e) asm volatile("" : "+v"(acc[e].re), "+v"(acc[e].im));
+}
+
+// one hop of the item kernel: neighbour spinor at checkerboard index nb
+// (other parity), link at (lpar, lcb) read from global memory
 template <typename S, int NE, int MU, int SG, bool FWD, int NR>
 __device__ __forceinline__ void hop(const DKArgs &a, int64_t nb, int lpar, int64_t lcb, typename Fmt<S>::R bsign,
                                     const int rhs[NR], cx<typename Fmt<S>::R> acc[NR][12])
@@ -89,42 +128,83 @@ __device__ __forceinline__ void hop(const DKArgs &a, int64_t nb, int lpar, int64
     for (int r = 0; r < NR; ++r) {
         cx<R> psi[12];
         load_spinor<S>(a.in, Vh, rhs[r], nb, psi);
-        cx<R> h[6];
-        project<R, MU, SG>(psi, h);
-        if constexpr (MU == 3) {
-#pragma unroll
-            for (int e = 0; e < 6; ++e) h[e] = bsign * h[e];
-        }
-        cx<R> gg[6];
-#pragma unroll
-        for (int sp = 0; sp < 2; ++sp)
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                cx<R> t = {R(0), R(0)};
-#pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    if constexpr (FWD)
-                        cmac(t, u[3 * i + j], h[3 * sp + j]);
-                    else
-                        cmac_conj(t, u[3 * j + i], h[3 * sp + j]);
-                }
-                gg[3 * sp + i] = t;
-            }
-        reconstruct<R, MU, SG>(acc[r], gg);
+        hop_mul<R, MU, SG, FWD>(u, psi, bsign, acc[r]);
     }
-    // Pin the accumulators here: this forces the hop's arithmetic to finish
-    // before the next hop's loads issue.  Without it the compiler issues all
-    // eight neighbours' loads first and runs out of registers.
 #pragma unroll
-    for (int r = 0; r < NR; ++r)
-#pragma unroll
-        for (int e = 0; e < 12; ++e) asm volatile("" : "+v"(acc[r][e].re), "+v"(acc[r][e].im));
+    for (int r = 0; r < NR; ++r) pin_acc<R>(acc[r]);
 }
 
 template <int EPI>
 constexpr int nparts_c()
 {
     return EPI == EPI_XPAY_DOT ? 2 : EPI == EPI_XPAY_TS ? 3 : (EPI == EPI_XPAY_NRM || EPI == EPI_XMY_NRM) ? 1 : 0;
+}
+
+// Epilogue for one right-hand side at one site: out = a * acc (PLAIN) or
+// x + a * acc (the XPAY family, with x - y in place of x for XMY), plus this
+// site's share of the epilogue's reductions in part[].
+template <typename S, int EPI>
+__device__ __forceinline__ void epilogue(const DKArgs &a, int rhs, int64_t cb, const cx<typename Fmt<S>::R> acc[12],
+                                         double part[])
+{
+    using R = typename Fmt<S>::R;
+    const R coef = R(a.a);
+    cx<R> o[12];
+    if constexpr (EPI == EPI_PLAIN) {
+#pragma unroll
+        for (int e = 0; e < 12; ++e) o[e] = coef * acc[e];
+    } else {
+        cx<R> xv[12];
+        load_spinor<S>(a.x, a.g.Vh, rhs, cb, xv);
+        if constexpr (EPI == EPI_XMY_NRM) {
+            cx<R> yv[12];
+            load_spinor<S>(a.y, a.g.Vh, rhs, cb, yv);
+#pragma unroll
+            for (int e = 0; e < 12; ++e) xv[e] = xv[e] - yv[e];
+        }
+#pragma unroll
+        for (int e = 0; e < 12; ++e) {
+            o[e].re = fma(coef, acc[e].re, xv[e].re);
+            o[e].im = fma(coef, acc[e].im, xv[e].im);
+        }
+        if constexpr (EPI == EPI_XPAY_DOT) {
+            cx<R> yv[12];
+            load_spinor<S>(a.y, a.g.Vh, rhs, cb, yv);
+#pragma unroll
+            for (int e = 0; e < 12; ++e) {
+                part[0] += (double)yv[e].re * o[e].re + (double)yv[e].im * o[e].im;
+                part[1] += (double)yv[e].re * o[e].im - (double)yv[e].im * o[e].re;
+            }
+        } else if constexpr (EPI == EPI_XPAY_TS) {
+#pragma unroll
+            for (int e = 0; e < 12; ++e) {
+                part[0] += (double)o[e].re * xv[e].re + (double)o[e].im * xv[e].im;
+                part[1] += (double)o[e].re * xv[e].im - (double)o[e].im * xv[e].re;
+                part[2] += (double)o[e].re * o[e].re + (double)o[e].im * o[e].im;
+            }
+        }
+    }
+    if constexpr (EPI == EPI_XPAY_NRM || EPI == EPI_XMY_NRM) {
+#pragma unroll
+        for (int e = 0; e < 12; ++e) part[0] += (double)o[e].re * o[e].re + (double)o[e].im * o[e].im;
+    }
+    store_spinor<S>(a.out, a.g.Vh, rhs, cb, o);
+}
+
+// neighbour checkerboard indices (x+, x-, y+, y-, z+, z-, t+, t-) of site
+// cb of parity p
+__device__ __forceinline__ void neighbours(const Geom &g, int cb, const Site &s, int nb[8])
+{
+    const int bx = cb - (s.x >> 1);
+    const int xf = s.x + 1 == g.X ? 0 : s.x + 1, xb = s.x == 0 ? g.X - 1 : s.x - 1;
+    nb[0] = bx + (xf >> 1);
+    nb[1] = bx + (xb >> 1);
+    nb[2] = s.y + 1 == g.Y ? cb - (g.Y - 1) * g.sY : cb + g.sY;
+    nb[3] = s.y == 0 ? cb + (g.Y - 1) * g.sY : cb - g.sY;
+    nb[4] = s.z + 1 == g.Z ? cb - (g.Z - 1) * g.sZ : cb + g.sZ;
+    nb[5] = s.z == 0 ? cb + (g.Z - 1) * g.sZ : cb - g.sZ;
+    nb[6] = s.t + 1 == g.T ? cb - (g.T - 1) * g.sT : cb + g.sT;
+    nb[7] = s.t == 0 ? cb + (g.T - 1) * g.sT : cb - g.sT;
 }
 
 // One work item: site block sb of right-hand-side group grp, item L = grp * nblk + sb.
@@ -165,92 +245,29 @@ __device__ __forceinline__ void dslash_item(const DKArgs &a, int L, double *red)
     if (valid) {
         const int p = a.parity, q = 1 - p;
         const Site s = decode(g, cb, p);
-        const int64_t base_x = cb - (s.x >> 1);
+        int nb[8];
+        neighbours(g, cb, s, nb);
         constexpr int SF = DAG ? +1 : -1;  // forward projector 1 + SF g
         constexpr int SB = -SF;            // backward projector
         const R one = R(1);
-        // x
-        {
-            int xf = s.x + 1 == g.X ? 0 : s.x + 1;
-            int xb = s.x == 0 ? g.X - 1 : s.x - 1;
-            hop<S, NE, 0, SF, true, NR>(a, base_x + (xf >> 1), p, cb, one, rhs, acc);
-            int64_t nbb = base_x + (xb >> 1);
-            hop<S, NE, 0, SB, false, NR>(a, nbb, q, nbb, one, rhs, acc);
-        }
-        // y
-        {
-            int64_t nf = s.y + 1 == g.Y ? cb - (int64_t)(g.Y - 1) * g.sY : cb + g.sY;
-            int64_t nbb = s.y == 0 ? cb + (int64_t)(g.Y - 1) * g.sY : cb - g.sY;
-            hop<S, NE, 1, SF, true, NR>(a, nf, p, cb, one, rhs, acc);
-            hop<S, NE, 1, SB, false, NR>(a, nbb, q, nbb, one, rhs, acc);
-        }
-        // z
-        {
-            int64_t nf = s.z + 1 == g.Z ? cb - (int64_t)(g.Z - 1) * g.sZ : cb + g.sZ;
-            int64_t nbb = s.z == 0 ? cb + (int64_t)(g.Z - 1) * g.sZ : cb - g.sZ;
-            hop<S, NE, 2, SF, true, NR>(a, nf, p, cb, one, rhs, acc);
-            hop<S, NE, 2, SB, false, NR>(a, nbb, q, nbb, one, rhs, acc);
-        }
-        // t, with the boundary sign on the wrapping hops
-        {
-            const bool lastt = s.t + 1 == g.T, firstt = s.t == 0;
-            int64_t nf = lastt ? cb - (int64_t)(g.T - 1) * g.sT : cb + g.sT;
-            int64_t nbb = firstt ? cb + (int64_t)(g.T - 1) * g.sT : cb - g.sT;
-            R bf = (g.tap && lastt) ? R(-1) : R(1);
-            R bb = (g.tap && firstt) ? R(-1) : R(1);
-            hop<S, NE, 3, SF, true, NR>(a, nf, p, cb, bf, rhs, acc);
-            hop<S, NE, 3, SB, false, NR>(a, nbb, q, nbb, bb, rhs, acc);
-        }
+        const R bf = (g.tap && s.t + 1 == g.T) ? R(-1) : R(1);
+        const R bb = (g.tap && s.t == 0) ? R(-1) : R(1);
+        hop<S, NE, 0, SF, true, NR>(a, nb[0], p, cb, one, rhs, acc);
+        hop<S, NE, 0, SB, false, NR>(a, nb[1], q, nb[1], one, rhs, acc);
+        hop<S, NE, 1, SF, true, NR>(a, nb[2], p, cb, one, rhs, acc);
+        hop<S, NE, 1, SB, false, NR>(a, nb[3], q, nb[3], one, rhs, acc);
+        hop<S, NE, 2, SF, true, NR>(a, nb[4], p, cb, one, rhs, acc);
+        hop<S, NE, 2, SB, false, NR>(a, nb[5], q, nb[5], one, rhs, acc);
+        hop<S, NE, 3, SF, true, NR>(a, nb[6], p, cb, bf, rhs, acc);
+        hop<S, NE, 3, SB, false, NR>(a, nb[7], q, nb[7], bb, rhs, acc);
     }
 
-    const R coef = R(a.a);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         double part[NP > 0 ? NP : 1];
 #pragma unroll
         for (int k = 0; k < (NP > 0 ? NP : 1); ++k) part[k] = 0.0;
-        if (valid && live[r]) {
-            cx<R> o[12];
-            if constexpr (EPI == EPI_PLAIN) {
-#pragma unroll
-                for (int e = 0; e < 12; ++e) o[e] = coef * acc[r][e];
-            } else {
-                cx<R> xv[12];
-                load_spinor<S>(a.x, g.Vh, rhs[r], cb, xv);
-                if constexpr (EPI == EPI_XMY_NRM) {
-                    cx<R> yv[12];
-                    load_spinor<S>(a.y, g.Vh, rhs[r], cb, yv);
-#pragma unroll
-                    for (int e = 0; e < 12; ++e) xv[e] = xv[e] - yv[e];
-                }
-#pragma unroll
-                for (int e = 0; e < 12; ++e) {
-                    o[e].re = fma(coef, acc[r][e].re, xv[e].re);
-                    o[e].im = fma(coef, acc[r][e].im, xv[e].im);
-                }
-                if constexpr (EPI == EPI_XPAY_DOT) {
-                    cx<R> yv[12];
-                    load_spinor<S>(a.y, g.Vh, rhs[r], cb, yv);
-#pragma unroll
-                    for (int e = 0; e < 12; ++e) {
-                        part[0] += (double)yv[e].re * o[e].re + (double)yv[e].im * o[e].im;
-                        part[1] += (double)yv[e].re * o[e].im - (double)yv[e].im * o[e].re;
-                    }
-                } else if constexpr (EPI == EPI_XPAY_TS) {
-#pragma unroll
-                    for (int e = 0; e < 12; ++e) {
-                        part[0] += (double)o[e].re * xv[e].re + (double)o[e].im * xv[e].im;
-                        part[1] += (double)o[e].re * xv[e].im - (double)o[e].im * xv[e].re;
-                        part[2] += (double)o[e].re * o[e].re + (double)o[e].im * o[e].im;
-                    }
-                }
-            }
-            if constexpr (EPI == EPI_XPAY_NRM || EPI == EPI_XMY_NRM) {
-#pragma unroll
-                for (int e = 0; e < 12; ++e) part[0] += (double)o[e].re * o[e].re + (double)o[e].im * o[e].im;
-            }
-            store_spinor<S>(a.out, g.Vh, rhs[r], cb, o);
-        }
+        if (valid && live[r]) epilogue<S, EPI>(a, rhs[r], cb, acc[r], part);
         if constexpr (NP > 0) {
             block_sum<NP>(part, red);
             if (threadIdx.x == 0 && live[r]) {
@@ -272,7 +289,128 @@ __global__ __launch_bounds__(256) void dslash_kernel(Segs<DKArgs> B)
     for_each_item(B, [&](const DKArgs &a, int L) { dslash_item<S, NE, DAG, EPI, NR>(a, L, red); });
 }
 
+// ---------------------------------------------------------------- LDS-link kernel
+//
+// A workgroup owns 64 consecutive checkerboard sites (one wavefront wide) and
+// keeps their 8 x NE link matrices in LDS; its LANES wavefronts then walk the
+// right-hand sides (wavefront w takes w, w + LANES, ...), so every link is
+// read from memory once per launch instead of once per right-hand side.
+// Site blocks are grouped into regions of rb consecutive blocks; region i
+// runs on XCD i mod 8, and the grid is sized so that a region's blocks are
+// resident together and advance through the right-hand sides in step: the
+// neighbour spinors they share are then fetched into that XCD's L2 once.
+// The partial sums of a reducing epilogue are per wavefront, i.e. per
+// (right-hand side, 64-site block).
+constexpr int LDS_SITES = 64;
+
+template <typename S, int NE>
+constexpr int lds_link_bytes()
+{
+    return 8 * NE * LDS_SITES * (int)sizeof(typename Fmt<S>::E);
+}
+
+template <typename S, int NE, bool DAG, int EPI, int LANES>
+__global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArgs> B, int rb)
+{
+    using R = typename Fmt<S>::R;
+    using E = typename Fmt<S>::E;
+    constexpr int NP = nparts_c<EPI>();
+    constexpr int SF = DAG ? +1 : -1;
+    constexpr int SB = -SF;
+    __shared__ E lk[8 * NE * LDS_SITES];
+
+    const int sl = threadIdx.x & (LDS_SITES - 1), w = threadIdx.x / LDS_SITES;
+    const int total = B.prefix[B.n];
+    const int nreg = (total + rb - 1) / rb;
+    const int xcd = blockIdx.x % 8, j = blockIdx.x / 8;
+    const int nbx = gridDim.x / 8 + (xcd < (int)(gridDim.x % 8) ? 1 : 0);
+    const int myreg = nreg / 8 + (xcd < nreg % 8 ? 1 : 0);
+    const int cnt = myreg * rb;
+    for (int it = j; it < cnt; it += nbx) {
+        const int ri = it / rb;
+        const int item = (xcd + 8 * ri) * rb + (it - ri * rb);
+        if (item >= total) continue;  // uniform across the block
+        int sg = 0;
+        while (sg + 1 < B.n && item >= B.prefix[sg + 1]) ++sg;
+        const DKArgs &a = B.a[sg];
+        const Geom &g = a.g;
+        const int sb = item - B.prefix[sg];
+        const int cb = sb * LDS_SITES + sl;
+        const bool valid = cb < g.Vh;
+        const int p = a.parity, q = 1 - p;
+        Site s = {0, 0, 0, 0};
+        int nb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (valid) {
+            s = decode(g, cb, p);
+            neighbours(g, cb, s, nb);
+        }
+        __syncthreads();  // the previous item's links are no longer read
+        if (valid) {
+            for (int d = w; d < 8; d += LANES) {
+                const int mu = d >> 1, bwd = d & 1;
+                const int lcb = bwd ? nb[d] : cb;
+                const E *src = static_cast<const E *>(a.links) + ((int64_t)(mu * 2 + (bwd ? q : p)) * NE) * g.Vh + lcb;
+#pragma unroll
+                for (int e = 0; e < NE; ++e) lk[(d * NE + e) * LDS_SITES + sl] = src[(int64_t)e * g.Vh];
+            }
+        }
+        __syncthreads();
+
+        const R one = R(1);
+        const R bf = (g.tap && s.t + 1 == g.T) ? R(-1) : R(1);
+        const R bb = (g.tap && s.t == 0) ? R(-1) : R(1);
+        unsigned nlive = 0;
+        for (int r = w; r < a.nrhs; r += LANES) {  // uniform across the wavefront
+            if (a.active != nullptr && !a.active[r]) continue;
+            ++nlive;
+            double part[NP > 0 ? NP : 1];
+#pragma unroll
+            for (int k = 0; k < (NP > 0 ? NP : 1); ++k) part[k] = 0.0;
+            if (valid) {
+                cx<R> acc[12];
+#pragma unroll
+                for (int e = 0; e < 12; ++e) acc[e] = {R(0), R(0)};
+#pragma unroll
+                for (int d = 0; d < 8; ++d) {
+                    cx<R> u[9];
+#pragma unroll
+                    for (int e = 0; e < NE; ++e) u[e] = Fmt<S>::ld(lk, (d * NE + e) * LDS_SITES + sl);
+                    if constexpr (NE == 6) {
+                        u[6] = conj(u[1] * u[5] - u[2] * u[4]);
+                        u[7] = conj(u[2] * u[3] - u[0] * u[5]);
+                        u[8] = conj(u[0] * u[4] - u[1] * u[3]);
+                    }
+                    cx<R> psi[12];
+                    load_spinor<S>(a.in, g.Vh, r, nb[d], psi);
+                    switch (d) {
+                    case 0: hop_mul<R, 0, SF, true>(u, psi, one, acc); break;
+                    case 1: hop_mul<R, 0, SB, false>(u, psi, one, acc); break;
+                    case 2: hop_mul<R, 1, SF, true>(u, psi, one, acc); break;
+                    case 3: hop_mul<R, 1, SB, false>(u, psi, one, acc); break;
+                    case 4: hop_mul<R, 2, SF, true>(u, psi, one, acc); break;
+                    case 5: hop_mul<R, 2, SB, false>(u, psi, one, acc); break;
+                    case 6: hop_mul<R, 3, SF, true>(u, psi, bf, acc); break;
+                    default: hop_mul<R, 3, SB, false>(u, psi, bb, acc); break;
+                    }
+                    pin_acc<R>(acc);
+                }
+                epilogue<S, EPI>(a, r, cb, acc, part);
+            }
+            if constexpr (NP > 0) {
+#pragma unroll
+                for (int k = 0; k < NP; ++k) part[k] = wave_sum(part[k]);
+                if (sl == 0) {
+                    double *dst = a.partials + ((int64_t)r * a.nblk + sb) * NP;
+#pragma unroll
+                    for (int k = 0; k < NP; ++k) dst[k] = part[k];
+                }
+            }
+        }
+        if (a.live_count != nullptr && sl == 0 && nlive > 0) atomicAdd(a.live_count, nlive);
+    }
+}
+
 template <typename S>
-void launch_dslash_t(const DslashCall *c, int nseg, int nr, int bs, int persistent, hipStream_t s);
+void launch_dslash_t(const DslashCall *c, int nseg, int kind, int nr, int bs, int persistent, hipStream_t s);
 
 }  // namespace dl

@@ -7,8 +7,19 @@
 namespace dl {
 
 template <typename S, int NE, bool DAG, int EPI>
-static void dslash_go_nr(const Segs<DKArgs> &B, int nr, int grid, int bs, hipStream_t s)
+static void dslash_go_nr(const Segs<DKArgs> &B, int kind, int nr, int grid, int bs, int rb, hipStream_t s)
 {
+    if constexpr (lds_link_bytes<S, NE>() <= 65536) {
+        if (kind == 1) {
+            if (nr == 4)
+                hipLaunchKernelGGL((dslash_lds_kernel<S, NE, DAG, EPI, 4>), dim3(grid), dim3(4 * LDS_SITES), 0, s, B, rb);
+            else if (nr == 2)
+                hipLaunchKernelGGL((dslash_lds_kernel<S, NE, DAG, EPI, 2>), dim3(grid), dim3(2 * LDS_SITES), 0, s, B, rb);
+            else
+                hipLaunchKernelGGL((dslash_lds_kernel<S, NE, DAG, EPI, 1>), dim3(grid), dim3(LDS_SITES), 0, s, B, rb);
+            return;
+        }
+    }
     if (nr == 2)
         hipLaunchKernelGGL((dslash_kernel<S, NE, DAG, EPI, 2>), dim3(grid), dim3(bs), 0, s, B);
     else
@@ -16,24 +27,41 @@ static void dslash_go_nr(const Segs<DKArgs> &B, int nr, int grid, int bs, hipStr
 }
 
 template <typename S, int NE, bool DAG>
-static void dslash_go_epi(const Segs<DKArgs> &B, int epi, int nr, int grid, int bs, hipStream_t s)
+static void dslash_go_epi(const Segs<DKArgs> &B, int epi, int kind, int nr, int grid, int bs, int rb, hipStream_t s)
 {
     switch (epi) {
-    case EPI_PLAIN: dslash_go_nr<S, NE, DAG, EPI_PLAIN>(B, nr, grid, bs, s); break;
-    case EPI_XPAY: dslash_go_nr<S, NE, DAG, EPI_XPAY>(B, nr, grid, bs, s); break;
-    case EPI_XPAY_DOT: dslash_go_nr<S, NE, DAG, EPI_XPAY_DOT>(B, nr, grid, bs, s); break;
-    case EPI_XPAY_TS: dslash_go_nr<S, NE, DAG, EPI_XPAY_TS>(B, nr, grid, bs, s); break;
-    case EPI_XPAY_NRM: dslash_go_nr<S, NE, DAG, EPI_XPAY_NRM>(B, nr, grid, bs, s); break;
-    case EPI_XMY_NRM: dslash_go_nr<S, NE, DAG, EPI_XMY_NRM>(B, nr, grid, bs, s); break;
+    case EPI_PLAIN: dslash_go_nr<S, NE, DAG, EPI_PLAIN>(B, kind, nr, grid, bs, rb, s); break;
+    case EPI_XPAY: dslash_go_nr<S, NE, DAG, EPI_XPAY>(B, kind, nr, grid, bs, rb, s); break;
+    case EPI_XPAY_DOT: dslash_go_nr<S, NE, DAG, EPI_XPAY_DOT>(B, kind, nr, grid, bs, rb, s); break;
+    case EPI_XPAY_TS: dslash_go_nr<S, NE, DAG, EPI_XPAY_TS>(B, kind, nr, grid, bs, rb, s); break;
+    case EPI_XPAY_NRM: dslash_go_nr<S, NE, DAG, EPI_XPAY_NRM>(B, kind, nr, grid, bs, rb, s); break;
+    case EPI_XMY_NRM: dslash_go_nr<S, NE, DAG, EPI_XMY_NRM>(B, kind, nr, grid, bs, rb, s); break;
     default: break;
     }
 }
 
-// c[0..nseg): calls with the same precision, link format, adjoint flag and
-// epilogue; persistent > 0 caps the grid at that many blocks (a multiple of 8)
+// whether the LDS-link kernel exists for this storage precision and link format
 template <typename S>
-void launch_dslash_t(const DslashCall *c, int nseg, int nr, int bs, int persistent, hipStream_t s)
+bool dslash_lds_ok_t(int recon)
 {
+    return recon == 12 ? lds_link_bytes<S, 6>() <= 65536 : lds_link_bytes<S, 9>() <= 65536;
+}
+
+// c[0..nseg): calls with the same precision, link format, adjoint flag and
+// epilogue.  kind 0: the item kernel with nr right-hand sides per thread and
+// bs sites per workgroup; persistent > 0 caps its grid at that many blocks (a
+// multiple of 8).  kind 1: the LDS-link kernel with nr wavefronts per
+// workgroup and regions of `persistent` site blocks.
+template <typename S>
+void launch_dslash_t(const DslashCall *c, int nseg, int kind, int nr, int bs, int persistent, hipStream_t s)
+{
+    if (kind == 1 && !dslash_lds_ok_t<S>(c[0].recon)) {
+        kind = 0;
+        nr = 1;
+        bs = 256;
+        persistent = 0;
+    }
+    if (kind == 1) bs = LDS_SITES;
     Segs<DKArgs> B;
     B.n = nseg;
     B.prefix[0] = 0;
@@ -52,21 +80,29 @@ void launch_dslash_t(const DslashCall *c, int nseg, int nr, int bs, int persiste
         a.partials = c[k].partials;
         a.active = c[k].active;
         a.live_count = c[k].live_count;
-        B.prefix[k + 1] = B.prefix[k] + a.nblk * ((c[k].nrhs + nr - 1) / nr);
+        const int groups = kind == 1 ? 1 : (c[k].nrhs + nr - 1) / nr;
+        B.prefix[k + 1] = B.prefix[k] + a.nblk * groups;
     }
     const int total = B.prefix[nseg];
-    const int grid = (persistent > 0 && total > persistent) ? persistent : total;
+    int grid, rb = 0;
+    if (kind == 1) {
+        rb = persistent > 0 ? persistent : 64;
+        const int nreg = (total + rb - 1) / rb;
+        grid = 8 * ((nreg + 7) / 8) * rb;
+    } else {
+        grid = (persistent > 0 && total > persistent) ? persistent : total;
+    }
     const DslashCall &c0 = c[0];
     if (c0.recon == 12) {
         if (c0.dag)
-            dslash_go_epi<S, 6, true>(B, c0.epi, nr, grid, bs, s);
+            dslash_go_epi<S, 6, true>(B, c0.epi, kind, nr, grid, bs, rb, s);
         else
-            dslash_go_epi<S, 6, false>(B, c0.epi, nr, grid, bs, s);
+            dslash_go_epi<S, 6, false>(B, c0.epi, kind, nr, grid, bs, rb, s);
     } else {
         if (c0.dag)
-            dslash_go_epi<S, 9, true>(B, c0.epi, nr, grid, bs, s);
+            dslash_go_epi<S, 9, true>(B, c0.epi, kind, nr, grid, bs, rb, s);
         else
-            dslash_go_epi<S, 9, false>(B, c0.epi, nr, grid, bs, s);
+            dslash_go_epi<S, 9, false>(B, c0.epi, kind, nr, grid, bs, rb, s);
     }
 }
 

@@ -168,13 +168,19 @@ struct DslashCall {
 int launch_dslash(const DslashCall &c, hipStream_t s);
 std::vector<int> launch_dslash_batch(const std::vector<DslashCall> &calls, hipStream_t s);
 
-// launch configuration of the hopping kernel: right-hand sides per thread,
-// sites per workgroup and the persistent grid cap (0 = one block per item)
+// launch configuration of the hopping kernel.  kind 0 (item kernel):
+// right-hand sides per thread, sites per workgroup and the persistent grid
+// cap (0 = one block per item).  kind 1 (LDS-link kernel): nr wavefronts per
+// workgroup, 64 sites per workgroup, regions of `persistent` site blocks.
 struct TuneChoice {
-    int nr, bs, persistent;
+    int kind, nr, bs, persistent;
 };
 TuneChoice tune_lookup(const std::vector<DslashCall> &c, hipStream_t s);
-void launch_dslash_any(const std::vector<DslashCall> &c, int nr, int bs, int persistent, hipStream_t s);
+void launch_dslash_any(const std::vector<DslashCall> &c, const TuneChoice &t, hipStream_t s);
+// whether the LDS-link kernel serves this precision and link format (its
+// links must fit 64 KiB of LDS), and the sites per block a choice gives
+bool dslash_lds_ok(int prec, int recon);
+int dslash_block_sites(const DslashCall &c, const TuneChoice &t);
 int dslash_site_blocks(const Geom &g, int prec, int nrhs);
 
 // ---------------------------------------------------------------- Krylov vector kernels

@@ -1,25 +1,35 @@
 // dl_tune.cpp -- autotuner for the hopping kernel's launch configuration.
 //
-// The tunables are the number of right-hand sides a thread carries (1 or 2:
-// links loaded once serve both), the workgroup size (64, 128 or 256 sites)
-// and whether the grid is persistent (a capped number of workgroups looping
-// over the work items).  The first time a (precision, link format, adjoint,
+// Two kernels compete.  The item kernel's tunables are the number of
+// right-hand sides a thread carries (1 or 2: links loaded once serve both),
+// the workgroup size (64, 128 or 256 sites) and whether the grid is
+// persistent (a capped number of workgroups looping over the work items).
+// The LDS-link kernel's are the wavefronts per workgroup (1, 2 or 4
+// right-hand sides in flight per 64-site block) and the region size (32, 64
+// or 128 site blocks advancing together on one XCD).  The first time a
+// (precision, link format, adjoint,
 // epilogue, right-hand sides, lattices) combination is launched, each
 // candidate is timed
 // with HIP events on the real operands (every hopping launch is idempotent:
 // its output never aliases an input) and the fastest is kept, in memory and
-// in a text cache file (DL_TUNE_CACHE, default ~/.cache/dloops/tune_gfx950_v2.txt).
-// DL_TUNE=0 disables tuning and uses 1 right-hand side per thread with 256
-// sites per workgroup.  Tuning never runs while the stream is being captured.
+// in a text cache file (DL_TUNE_CACHE, default ~/.cache/dloops/tune_gfx950_v3.txt).
+// DL_TUNE=0 disables tuning and uses the LDS-link kernel with 2 wavefronts
+// and regions of 64 blocks where its links fit in LDS, else the item kernel
+// with 1 right-hand side per thread and 256 sites per workgroup;
+// DL_TUNE=item and DL_TUNE=lds pin those two choices (the latter where the
+// LDS-link kernel applies).  The variable is read at every lookup.  Tuning
+// never runs while the stream is being captured.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
 #include <sys/stat.h>
 #include <tuple>
+#include <vector>
 
 #include "dl_internal.hpp"
 
@@ -52,13 +62,43 @@ std::string cache_path()
 {
     if (const char *p = std::getenv("DL_TUNE_CACHE")) return p;
     const char *home = std::getenv("HOME");
-    return std::string(home ? home : "/tmp") + "/.cache/dloops/tune_gfx950_v2.txt";
+    return std::string(home ? home : "/tmp") + "/.cache/dloops/tune_gfx950_v3.txt";
 }
 
-bool tuning_enabled()
+// DL_TUNE: unset or anything else = tune; "0" = default; "item" / "lds" = pinned
+int tune_mode()
 {
     const char *e = std::getenv("DL_TUNE");
-    return !(e && e[0] == '0');
+    if (!e) return 0;
+    if (std::strcmp(e, "0") == 0) return 1;
+    if (std::strcmp(e, "item") == 0) return 2;
+    if (std::strcmp(e, "lds") == 0) return 3;
+    return 0;
+}
+
+// the candidate set; a cached choice outside it is ignored
+std::vector<TuneChoice> candidates(int prec, int recon)
+{
+    std::vector<TuneChoice> v;
+    for (int nr : {1, 2})
+        for (int bs : {64, 128, 256})
+            for (int pg : {0, PERSIST_GRID}) v.push_back(TuneChoice{0, nr, bs, pg});
+    if (dslash_lds_ok(prec, recon))
+        for (int lanes : {1, 2, 4})
+            for (int rb : {32, 64, 128}) v.push_back(TuneChoice{1, lanes, 64, rb});
+    return v;
+}
+
+bool valid_choice(const TuneChoice &t, int prec, int recon)
+{
+    for (const TuneChoice &c : candidates(prec, recon))
+        if (c.kind == t.kind && c.nr == t.nr && c.bs == t.bs && c.persistent == t.persistent) return true;
+    return false;
+}
+
+TuneChoice default_choice(int prec, int recon)
+{
+    return dslash_lds_ok(prec, recon) ? TuneChoice{1, 2, 64, 64} : TuneChoice{0, 1, 256, 0};
 }
 
 void load_locked()
@@ -67,12 +107,11 @@ void load_locked()
     g_loaded = true;
     FILE *f = std::fopen(cache_path().c_str(), "r");
     if (!f) return;
-    int v[12];
-    while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6],
-                       &v[7], &v[8], &v[9], &v[10], &v[11]) == 12) {
-        if ((v[9] == 1 || v[9] == 2) && (v[10] == 64 || v[10] == 128 || v[10] == 256) &&
-            (v[11] == 0 || v[11] == PERSIST_GRID))
-            g_cache[Key{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8]}] = TuneChoice{v[9], v[10], v[11]};
+    int v[13];
+    while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6],
+                       &v[7], &v[8], &v[9], &v[10], &v[11], &v[12]) == 13) {
+        const TuneChoice t{v[9], v[10], v[11], v[12]};
+        if (valid_choice(t, v[0], v[1])) g_cache[Key{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8]}] = t;
     }
     std::fclose(f);
 }
@@ -85,9 +124,9 @@ void save_locked(const Key &k, const TuneChoice &t)
         if (i == dir.size() || dir[i] == '/') mkdir(dir.substr(0, i).c_str(), 0755);
     FILE *f = std::fopen(path.c_str(), "a");
     if (!f) return;
-    std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
-                 std::get<3>(k), std::get<4>(k), std::get<5>(k), std::get<6>(k), std::get<7>(k), std::get<8>(k), t.nr,
-                 t.bs, t.persistent);
+    std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+                 std::get<3>(k), std::get<4>(k), std::get<5>(k), std::get<6>(k), std::get<7>(k), std::get<8>(k), t.kind,
+                 t.nr, t.bs, t.persistent);
     std::fclose(f);
 }
 
@@ -102,8 +141,10 @@ bool aliases(const std::vector<DslashCall> &cs)
 
 TuneChoice tune_lookup(const std::vector<DslashCall> &c, hipStream_t s)
 {
-    const TuneChoice dflt{1, 256, 0};
-    if (!tuning_enabled() || aliases(c)) return dflt;
+    const TuneChoice dflt = default_choice(c[0].prec, c[0].recon);
+    const int mode = tune_mode();
+    if (mode == 2) return TuneChoice{0, 1, 256, 0};
+    if (mode == 1 || mode == 3 || aliases(c)) return dflt;
     const Key k = make_key(c);
     std::lock_guard<std::mutex> lk(g_mu);
     load_locked();
@@ -124,27 +165,23 @@ TuneChoice tune_lookup(const std::vector<DslashCall> &c, hipStream_t s)
     float best_ms = 1e30f;
     std::vector<DslashCall> t = c;
     for (DslashCall &d : t) d.live_count = nullptr;
-    for (int nr : {1, 2}) {
-        for (int bs : {64, 128, 256}) {
-            for (int pg : {0, PERSIST_GRID}) {
-                launch_dslash_any(t, nr, bs, pg, s);  // warm
-                int reps = 1;
-                float ms = 0;
-                for (int attempt = 0; attempt < 3; ++attempt) {
-                    (void)hipEventRecord(e0, s);
-                    for (int r = 0; r < reps; ++r) launch_dslash_any(t, nr, bs, pg, s);
-                    (void)hipEventRecord(e1, s);
-                    (void)hipEventSynchronize(e1);
-                    (void)hipEventElapsedTime(&ms, e0, e1);
-                    if (ms > 1.0f || reps >= 64) break;
-                    reps *= 8;
-                }
-                const float per = ms / reps;
-                if (hipGetLastError() == hipSuccess && per < best_ms) {
-                    best_ms = per;
-                    best = TuneChoice{nr, bs, pg};
-                }
-            }
+    for (const TuneChoice &cand : candidates(c[0].prec, c[0].recon)) {
+        launch_dslash_any(t, cand, s);  // warm
+        int reps = 1;
+        float ms = 0;
+        for (int attempt = 0; attempt < 3; ++attempt) {
+            (void)hipEventRecord(e0, s);
+            for (int r = 0; r < reps; ++r) launch_dslash_any(t, cand, s);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms > 1.0f || reps >= 64) break;
+            reps *= 8;
+        }
+        const float per = ms / reps;
+        if (hipGetLastError() == hipSuccess && per < best_ms) {
+            best_ms = per;
+            best = cand;
         }
     }
     (void)hipEventDestroy(e0);
