@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--copy-reference", action="store_true",
                     help="first run a plain device copy (2 GiB read, 2 GiB written), the reference for hardware byte counters")
     ap.add_argument("--cpu-only", action="store_true", help="time only the CPU oracle sample")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the per-precision hopping-kernel sweep and the single-right-hand-side figures")
     return ap.parse_args()
 
 
@@ -117,10 +119,84 @@ def tsm_comparison(dl, G, w, L_plain, ms_plain):
     return out
 
 
+def copy_rate(torch):
+    """Achievable HBM rate of a plain device copy: 2 GiB read + 2 GiB written, event-timed."""
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    del a, b
+    return 2 * 8 * n / (ms * 1e-3) / 1e9
+
+
+def hop_rate(dl, torch, G, nrhs, prec, reps=3):
+    """Plain half-dslash launches of D applied to nrhs right-hand sides at one storage precision:
+    (launches, algorithmic GB/s, mean event-timed launch in us, launch configuration).  The first
+    application tunes; the profiled ones follow."""
+    V = G.lattice.V
+    x = torch.zeros((nrhs, V, 4, 3), dtype=torch.complex128, device="cuda")
+    x.real.normal_()
+    dl.apply(G, 0.15, dl.DL_OP_DHOP, x, prec=prec)
+    torch.cuda.synchronize()
+    dl.dl_profile_enable(True)
+    for _ in range(reps):
+        dl.apply(G, 0.15, dl.DL_OP_DHOP, x, prec=prec)
+    torch.cuda.synchronize()
+    n, ms, by = dl.dl_profile_read(3)
+    cfg = dl.dl_profile_config(3)
+    dl.dl_profile_enable(False)
+    del x
+    torch.cuda.empty_cache()
+    return n, by / (ms * 1e-3) / 1e9, ms / max(n, 1) * 1e3, cfg
+
+
+def dslash_sweep(dl, torch, G, copy_gbs):
+    """The plain half dslash D_oe / D_eo at every storage precision on the timed workload's batch
+    (16^3 x 32, 288 right-hand sides), the single-right-hand-side FP64 figure on the same lattice
+    (its 75 MB working set sits in the 256 MB Infinity Cache), and the single-right-hand-side FP64
+    figure on 24^3 x 48 (382 MB, larger than that cache)."""
+    import synth
+
+    out = {}
+    names = {dl.DL_F64: "f64", dl.DL_F32: "f32", dl.DL_F16: "f16", dl.DL_BF16: "bf16"}
+    for prec, nm in names.items():
+        n, gbs, us, cfg = hop_rate(dl, torch, G, 288, prec)
+        out[nm + "_288rhs"] = {"gbs": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                               "frac_copy": round(gbs / copy_gbs, 4), "avg_launch_us": round(us, 1),
+                               "launches": n, "config": list(cfg)}
+    n, gbs, us, cfg = hop_rate(dl, torch, G, 1, dl.DL_F64, reps=20)
+    out["f64_1rhs_cache_resident"] = {"gbs": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                                      "avg_launch_us": round(us, 1), "launches": n, "config": list(cfg)}
+    w = synth.WORKLOADS["grad_24x24x24x48"]
+    U = synth.gauge_field(w["dims"], w["eps"], w["gauge_seed"])
+    G2 = dl.Gauge(dl.Lattice(w["dims"], 1), U, precs=(dl.DL_F64,), recon=12)
+    n, gbs, us, cfg = hop_rate(dl, torch, G2, 1, dl.DL_F64, reps=20)
+    out["f64_1rhs_24x24x24x48"] = {"gbs": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                                   "frac_copy": round(gbs / copy_gbs, 4), "avg_launch_us": round(us, 1),
+                                   "launches": n, "config": list(cfg)}
+    del G2
+    return out
+
+
 def synth_workload(name):
     import synth
 
     return synth.WORKLOADS[name]
+
+
+# Memory-side bytes per launch of the plain FP64 hopping kernel, from the two
+# rocprofv3 counter runs of profiles/dslash_plain_f64_16x16x16x32_288rhs.md
+# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, KiB -> bytes, mean over the 116
+# dispatches of warm-up + one step), keyed by the launch configuration they
+# were taken with.  Another configuration reports null.
+PROFILED_TRAFFIC = {(1, 2, 64, 128): 12.09e9}
 
 
 def kernel_name(cfg):
@@ -159,7 +235,7 @@ def main():
     dims, kappa = w["dims"], w["kappa"]
     U = synth.gauge_field(dims, w["eps"], w["gauge_seed"])
     lat = dl.Lattice(dims, 1)
-    G = dl.Gauge(lat, U, precs=(dl.DL_F64, dl.DL_F32, dl.DL_F16), recon=12)
+    G = dl.Gauge(lat, U, precs=(dl.DL_F64, dl.DL_F32, dl.DL_F16, dl.DL_BF16), recon=12)
     stream = torch.cuda.current_stream()
     prm = dl.solve_params(tol=1e-10, maxiter=1000)
     gam = [0, 15]
@@ -237,7 +313,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(plain_gbs / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": PROFILED_TRAFFIC.get(tuple(cfg)),
+            "traffic_unit": "bytes per launch (L2 fill + write-back, rocprofv3 FETCH_SIZE/WRITE_SIZE)",
             "launches": n_p,
             "avg_launch_us": round(ms_p / max(n_p, 1) * 1e3, 1),
             "algorithmic_bytes_per_launch": round(by_p / max(n_p, 1)),
@@ -245,6 +322,11 @@ def main():
     }
     if not args.no_tsm:
         out["tsm"] = tsm_comparison(dl, G, w, L, ms_step)
+    if not args.no_sweep:
+        cg = copy_rate(torch)
+        out["copy_reference_gbs"] = round(cg, 1)
+        out["roofline"]["frac_of_copy"] = round(plain_gbs / cg, 4)
+        out["dslash_by_precision"] = dslash_sweep(dl, torch, G, cg)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
