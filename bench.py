@@ -306,6 +306,10 @@ def main():
             "sources_traces": round(ms_t / args.steps, 2),
         },
         "dslash_launches_per_step": n_d // args.steps,
+        "kernel_gbs": {
+            "dslash": round(dslash_gbs, 1),
+            "krylov_vectors": round(by_b / (ms_b * 1e-3) / 1e9, 1),
+        },
         "roofline": {
             "kernel": kernel_name(cfg),
             "bound": "hbm",

@@ -111,7 +111,7 @@ static const int PROF_SLOTS = 1 << 16;
 
 static void prof_drain_locked();
 
-static bool capturing(hipStream_t s)
+bool capturing(hipStream_t s)
 {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     return hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;

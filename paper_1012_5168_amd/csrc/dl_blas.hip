@@ -22,6 +22,12 @@ __device__ __forceinline__ cx<R> ld_c(const double *p) { return {R(p[0]), R(p[1]
 
 __device__ __forceinline__ bool masked_off(const int *mask, int rhs) { return mask != nullptr && !mask[rhs]; }
 
+// profiling: the first block of a live right-hand side counts it once
+__device__ __forceinline__ void count_live(unsigned *live, int blk)
+{
+    if (live != nullptr && blk == 0 && threadIdx.x == 0) atomicAdd(live, 1u);
+}
+
 // ---------------------------------------------------------------- scalar kernels (one wave per rhs)
 
 // sum of partials [rhs][nblk][np] component k, fixed order
@@ -257,6 +263,7 @@ __device__ __forceinline__ void vec_item(const VSeg &a, int item, double *red)
     const int nb = (int)((a.Vh + BS - 1) / BS);
     const int rhs = item / nb, blk = item - rhs * nb;
     if (masked_off(a.mask, rhs)) return;
+    count_live(a.live, blk);
     const int64_t Vh = a.Vh;
     const int64_t cb = (int64_t)blk * BS + threadIdx.x;
     const bool valid = cb < Vh;
@@ -377,6 +384,7 @@ __global__ __launch_bounds__(BS) void copy_kernel(Segs<VSeg> B)
         const int nb = (int)((a.Vh + BS - 1) / BS);
         const int rhs = item / nb, blk = item - rhs * nb;
         if (masked_off(a.mask, rhs)) return;
+        count_live(a.live, blk);
         const int64_t cb = (int64_t)blk * BS + threadIdx.x;
         if (cb >= a.Vh) return;
         cx<RS> v[12];
@@ -397,6 +405,7 @@ __global__ __launch_bounds__(BS) void fold_kernel(Segs<VSeg> B)
         const int nb = (int)((a.Vh + BS - 1) / BS);
         const int rhs = item / nb, blk = item - rhs * nb;
         if (masked_off(a.mask, rhs)) return;
+        count_live(a.live, blk);
         const int64_t cb = (int64_t)blk * BS + threadIdx.x;
         if (cb >= a.Vh) return;
         cx<double> xv[12];
@@ -421,6 +430,7 @@ __global__ __launch_bounds__(BS) void sub_kernel(Segs<VSeg> B)
         const int nb = (int)((a.Vh + BS - 1) / BS);
         const int rhs = item / nb, blk = item - rhs * nb;
         if (masked_off(a.mask, rhs)) return;
+        count_live(a.live, blk);
         const int64_t cb = (int64_t)blk * BS + threadIdx.x;
         if (cb >= a.Vh) return;
         cx<double> av[12], bv[12];
@@ -451,11 +461,27 @@ int scalar_items(const SSeg &a) { return a.nrhs; }
 
 int grid_for(int total, int cap) { return total > cap ? cap : total; }
 
+double field_rhs_bytes(int prec, int64_t Vh) { return (double)Vh * 12 * elem_bytes(prec) + (prec == P16 ? 4.0 * Vh : 0.0); }
+
 double vec_bytes(int prec, const std::vector<VSeg> &segs, int nvec)
 {
     double b = 0;
-    for (const VSeg &a : segs) b += ((double)a.Vh * 12 * elem_bytes(prec) + (prec == P16 ? 4.0 * a.Vh : 0.0)) * a.nrhs;
+    for (const VSeg &a : segs) b += field_rhs_bytes(prec, a.Vh) * a.nrhs;
     return b * nvec;
+}
+
+// Profiled launches count the right-hand sides they process (masked ones
+// move no bytes): per_rhs(Vh) bytes for each counted one.
+template <typename F>
+std::vector<VSeg> counted_segs(const std::vector<VSeg> &segs, ProfScope &ps, hipStream_t s, F per_rhs)
+{
+    std::vector<VSeg> v = segs;
+    if (!prof_on() || capturing(s)) return v;
+    for (VSeg &a : v) {
+        a.live = prof_counter();
+        if (a.live) ps.parts.push_back({a.live, per_rhs(a.Vh), 0.0, 1.0});
+    }
+    return v;
 }
 
 template <int OP>
@@ -505,7 +531,9 @@ void vec_launch(int op, int prec, const std::vector<VSeg> &segs, hipStream_t s)
 {
     static const int nvec[] = {4, 3, 7, 6, 3, 1, 1, 2};
     ProfScope ps(PROF_BLAS, vec_bytes(prec, segs, nvec[op]), s);
-    Segs<VSeg> B = make_segs(segs, vec_items);
+    const std::vector<VSeg> sg =
+        counted_segs(segs, ps, s, [&](int64_t Vh) { return nvec[op] * field_rhs_bytes(prec, Vh); });
+    Segs<VSeg> B = make_segs(sg, vec_items);
     const int grid = grid_for(B.prefix[B.n], PERSIST);
     switch (op) {
     case V_BICG_P: vec_dispatch<V_BICG_P>(prec, B, grid, s); break;
@@ -522,7 +550,9 @@ void vec_launch(int op, int prec, const std::vector<VSeg> &segs, hipStream_t s)
 void copy_launch(int prec_dst, int prec_src, const std::vector<VSeg> &segs, hipStream_t s)
 {
     ProfScope ps(PROF_BLAS, vec_bytes(prec_dst, segs, 1) + vec_bytes(prec_src, segs, 1), s);
-    Segs<VSeg> B = make_segs(segs, vec_items);
+    const std::vector<VSeg> sg = counted_segs(
+        segs, ps, s, [&](int64_t Vh) { return field_rhs_bytes(prec_dst, Vh) + field_rhs_bytes(prec_src, Vh); });
+    Segs<VSeg> B = make_segs(sg, vec_items);
     const int grid = grid_for(B.prefix[B.n], PERSIST);
     switch (prec_dst) {
     case P64: copy_from<double>(prec_src, B, grid, s); break;
@@ -535,7 +565,9 @@ void copy_launch(int prec_dst, int prec_src, const std::vector<VSeg> &segs, hipS
 void fold_launch(int prec, const std::vector<VSeg> &segs, hipStream_t s)
 {
     ProfScope ps(PROF_BLAS, vec_bytes(P64, segs, 2) + vec_bytes(prec, segs, 2), s);
-    Segs<VSeg> B = make_segs(segs, vec_items);
+    const std::vector<VSeg> sg = counted_segs(
+        segs, ps, s, [&](int64_t Vh) { return 2 * field_rhs_bytes(P64, Vh) + 2 * field_rhs_bytes(prec, Vh); });
+    Segs<VSeg> B = make_segs(sg, vec_items);
     const int grid = grid_for(B.prefix[B.n], PERSIST);
     switch (prec) {
     case P64: hipLaunchKernelGGL(fold_kernel<double>, dim3(grid), dim3(BS), 0, s, B); break;
@@ -548,7 +580,8 @@ void fold_launch(int prec, const std::vector<VSeg> &segs, hipStream_t s)
 void sub_launch(const std::vector<VSeg> &segs, hipStream_t s)
 {
     ProfScope ps(PROF_BLAS, vec_bytes(P64, segs, 3), s);
-    Segs<VSeg> B = make_segs(segs, vec_items);
+    const std::vector<VSeg> sg = counted_segs(segs, ps, s, [&](int64_t Vh) { return 3 * field_rhs_bytes(P64, Vh); });
+    Segs<VSeg> B = make_segs(sg, vec_items);
     hipLaunchKernelGGL(sub_kernel, dim3(grid_for(B.prefix[B.n], PERSIST)), dim3(BS), 0, s, B);
 }
 

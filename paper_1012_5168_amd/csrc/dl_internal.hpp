@@ -122,6 +122,7 @@ struct ProfScope {
 // a zeroed device counter for the next profiled launch (null when profiling is off)
 unsigned *prof_counter();
 bool prof_on();
+bool capturing(hipStream_t s);  // the stream is recording a graph
 
 // ---------------------------------------------------------------- dslash
 
@@ -214,6 +215,7 @@ struct VSeg {
     int64_t Vh = 0;
     int nrhs = 0;
     double *parts = nullptr;    // [nrhs][blas_blocks(Vh)][np] for the reducing operations
+    unsigned *live = nullptr;   // profiling: incremented once per right-hand side processed
 };
 enum VOp { V_BICG_P = 0, V_BICG_S, V_BICG_XR, V_CG_XR, V_CG_P, V_ZERO, V_NORM2, V_DOT };
 void vec_launch(int op, int prec, const std::vector<VSeg> &segs, hipStream_t s);
