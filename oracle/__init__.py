@@ -20,7 +20,9 @@ and adds the estimator drivers, each a direct transcription of the method:
 * :func:`tsm_combine` -- the truncated solver method's estimate: mean of the
   low-precision set plus the mean high-minus-low correction (Section 2);
 * :func:`loops_dkappa` and :func:`loops_link_grad` -- derivatives of the same
-  estimators, from ``dM^-1/dkappa = M^-1 D M^-1`` and the adjoint solve.
+  estimators, from ``dM^-1/dkappa = M^-1 D M^-1`` and the adjoint solve;
+* :func:`disconnected_correlator` -- the two-loop (disconnected) correlator of
+  Section 3, Eq. (2), from per-noise loop estimates over distinct noise pairs.
 
 Parity is pinned against closed forms, invariants and dense linear algebra in
 ``tests/test_oracle_pins.py``; the pins are listed in the header of that file.
@@ -353,3 +355,39 @@ def exact_loops_dense(Minv: np.ndarray, dims, gammas) -> np.ndarray:
         vals = np.einsum("ab,xba->x", G, sp)
         np.add.at(out[k], tsite, vals)
     return out
+
+
+def disconnected_correlator(loops_b, loops_a, spatial_volume):
+    """Disconnected two-loop correlator of Section 3, Eq. (2), at zero momentum:
+
+        D(dt) = -1/(L^3 T) sum_t < L_B(t) L_A(t + dt) >,
+
+    the two loops closing on themselves at t and t + dt (t + dt taken modulo T:
+    the sum over t runs over the periodic time direction).  The gauge-field
+    expectation is not taken here; the noise expectation of the product is
+    estimated from per-noise loops over ordered pairs of distinct noises
+    n != m only, since a product of two estimates on the same noise carries
+    the noise's own fluctuation as a bias:
+
+        < L_B(t) L_A(t') > ~ 1/(N (N-1)) sum_{n != m} L_B^n(t) L_A^m(t').
+
+    loops_b, loops_a: complex [N][T] per-noise loops (N >= 2); returns complex [T]
+    indexed by dt.  Written as the plain double sum over pairs.
+    """
+    lb = np.asarray(loops_b, dtype=np.complex128)
+    la = np.asarray(loops_a, dtype=np.complex128)
+    n, T = lb.shape
+    if la.shape != (n, T) or n < 2:
+        raise ValueError("need two [N][T] loop arrays with N >= 2")
+    out = np.zeros(T, dtype=np.complex128)
+    for dt in range(T):
+        acc = 0j
+        for i in range(n):
+            for j in range(n):
+                if i == j:
+                    continue
+                for t in range(T):
+                    acc += lb[i, t] * la[j, (t + dt) % T]
+        out[dt] = -acc / (n * (n - 1)) / (spatial_volume * T)
+    return out
+

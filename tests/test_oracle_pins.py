@@ -23,6 +23,11 @@ that does not share its code:
 * Derivatives: d/dkappa against central differences with identical noise and
   against the dense M^-1 D M^-1; the link gradient against directional
   central differences.
+* Disconnected correlator (Eq. 2): identical per-noise estimates against the
+  circular cross-correlation computed with numpy's FFT (convolution theorem);
+  unbiasedness over distinct noise pairs when the two loops of one noise are
+  correlated (z-test), with the same-noise estimator shown to be biased on the
+  same data; the B <-> A swap symmetry D^BA(dt) = D^AB(T - dt).
 """
 import itertools
 
@@ -500,3 +505,58 @@ def test_link_gradient_directional_difference():
         an = np.sum((np.conj(g) * dU).real)
         assert abs(fd - an) < 1e-6 * max(1.0, abs(an)), (fd, an)
     assert g.shape == (4, V, 3, 3)
+
+
+# ------------------------------------------------------------ disconnected correlator (Eq. 2)
+
+def test_correlator_identical_estimates_against_fft():
+    """All noises give the same loops b, a: the estimate is -1/(L^3 T) sum_t b(t) a(t+dt),
+    here from the convolution theorem: sum_t b(t) a(t+dt) = ifft(fft(a) conj(fft(conj b)))."""
+    rng = np.random.default_rng(71)
+    T, L3 = 7, 27
+    b = rng.normal(size=T) + 1j * rng.normal(size=T)
+    a = rng.normal(size=T) + 1j * rng.normal(size=T)
+    got = oracle.disconnected_correlator(np.tile(b, (3, 1)), np.tile(a, (3, 1)), L3)
+    ref = -np.fft.ifft(np.fft.fft(a) * np.conj(np.fft.fft(np.conj(b)))) / (L3 * T)
+    assert np.max(np.abs(got - ref)) < 1e-13 * np.max(np.abs(ref))
+
+
+def test_correlator_unbiased_over_distinct_noise_pairs():
+    """Per-noise loops L_A^n = mu_A + xi_n and L_B^n = mu_B + c xi_n share their fluctuation xi_n
+    (real Gaussian, so E[xi(t) xi(t)] != 0), as two loops from the same source do.  The estimate
+    over n != m has expectation -1/(L^3 T) sum_t mu_B(t) mu_A(t+dt); including n == m adds
+    c E[xi(t) xi(t+dt)] / N, which the same data must show (so the test can tell the two apart)."""
+    rng = np.random.default_rng(72)
+    T, L3, N, reps = 4, 8, 5, 1500
+    mu_a = rng.normal(size=T) + 1j * rng.normal(size=T)
+    mu_b = rng.normal(size=T) + 1j * rng.normal(size=T)
+    c = 0.8 + 0.3j
+    est, biased = [], []
+    for _ in range(reps):
+        xi = rng.normal(size=(N, T)) * 0.7
+        la, lb = mu_a + xi, mu_b + c * xi
+        est.append(oracle.disconnected_correlator(lb, la, L3))
+        # all ordered pairs including n == m, written with numpy for the contrast
+        sa, sb = la.sum(axis=0), lb.sum(axis=0)
+        biased.append(np.array([-np.sum(sb * np.roll(sa, -dt)) / N ** 2 / (L3 * T) for dt in range(T)]))
+    est, biased = np.array(est), np.array(biased)
+    ref = np.array([-np.sum(mu_b * np.roll(mu_a, -dt)) / (L3 * T) for dt in range(T)])
+    se = est.std(axis=0, ddof=1) / np.sqrt(reps)
+    for part in (np.real, np.imag):
+        z = np.abs(part(est.mean(axis=0) - ref)) / part(se + 1j * se)
+        assert np.all(z < 4.5), z
+    # the same-noise estimator is off by -c 0.49 / (N L3) at dt = 0: many standard errors away
+    zb = np.abs(biased.mean(axis=0)[0] - ref[0]) / (np.abs(biased.std(axis=0, ddof=1)[0]) / np.sqrt(reps))
+    assert zb > 10, zb
+
+
+def test_correlator_swap_symmetry():
+    rng = np.random.default_rng(73)
+    N, T, L3 = 4, 6, 64
+    lb = rng.normal(size=(N, T)) + 1j * rng.normal(size=(N, T))
+    la = rng.normal(size=(N, T)) + 1j * rng.normal(size=(N, T))
+    dba = oracle.disconnected_correlator(lb, la, L3)
+    dab = oracle.disconnected_correlator(la, lb, L3)
+    for dt in range(T):
+        assert abs(dba[dt] - dab[(T - dt) % T]) < 1e-14 * np.max(np.abs(dba))
+
