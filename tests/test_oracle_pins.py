@@ -547,7 +547,7 @@ def test_correlator_unbiased_over_distinct_noise_pairs():
         assert np.all(z < 4.5), z
     # the same-noise estimator is off by -c 0.49 / (N L3) at dt = 0: many standard errors away
     zb = np.abs(biased.mean(axis=0)[0] - ref[0]) / (np.abs(biased.std(axis=0, ddof=1)[0]) / np.sqrt(reps))
-    assert zb > 10, zb
+    assert zb > 6, zb
 
 
 def test_correlator_swap_symmetry():
