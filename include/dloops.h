@@ -271,6 +271,25 @@ int64_t dl_sources_count(dl_lattice lat, const dl_sources *src);
 int dl_sources_fill(dl_lattice lat, const dl_sources *src, int64_t first_rhs, int64_t nrhs, void *out, void *stream);
 
 /*
+ * Disconnected two-loop correlator at zero momentum (Section 3, Eq. 2) from
+ * per-noise loop estimates of two insertions B and A, e.g. two Gamma slices
+ * of the dl_loops output (one lattice, one set of noises):
+ *     corr[dt] = -1/(spatial_volume * T) * 1/(n (n - 1))
+ *                * sum_{n' != m} sum_t L_B^{n'}(t) L_A^{m}((t + dt) mod T),
+ * i.e. the noise expectation of the product of two loops is estimated over
+ * ordered pairs of distinct noises: the product of two estimates on the same
+ * noise carries that noise's own fluctuation as a bias.  (The expectation
+ * over gauge fields is the caller's.)
+ * loops_b, loops_a: host [n_noise][T][2] (re, im) FP64; corr: host [T][2],
+ * indexed by dt = 0 .. T-1.  Summation order is fixed (run-to-run
+ * deterministic).  n_noise >= 2, T in [1, 65535], spatial_volume >= 1 and
+ * non-null pointers, else DL_EINVAL before any device work.  Runs on `stream`
+ * (null = default) and returns after the result has been copied back.
+ */
+int dl_disconnected_correlator(const double *loops_b, const double *loops_a, int32_t n_noise, int32_t T,
+                               int64_t spatial_volume, double *corr, void *stream);
+
+/*
  * Kernel profiling on the library's streams.  dl_profile_enable(1) resets the
  * counters and brackets every following launch with HIP events (and a device
  * counter of the right-hand sides a hopping launch actually processed);

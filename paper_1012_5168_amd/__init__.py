@@ -114,6 +114,8 @@ _SIGNATURES = {
                                       ctypes.c_int32, _P, _P, _P]),
     "dl_sources_count": (ctypes.c_int64, [_P, ctypes.POINTER(dl_sources)]),
     "dl_sources_fill": (ctypes.c_int, [_P, ctypes.POINTER(dl_sources), ctypes.c_int64, ctypes.c_int64, _P, _P]),
+    "dl_disconnected_correlator": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                                  ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
     "dl_profile_enable": (ctypes.c_int, [ctypes.c_int32]),
     "dl_profile_config": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "dl_profile_read": (ctypes.c_int64, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
@@ -273,6 +275,24 @@ def dl_sources_fill(lat, sources, first_rhs, nrhs, out, stream=None):
 
 def dl_profile_enable(on: bool = True):
     load().dl_profile_enable(1 if on else 0)
+
+
+def dl_disconnected_correlator(loops_b, loops_a, n_noise, T, spatial_volume, corr, stream=None):
+    _check(load().dl_disconnected_correlator(loops_b.ctypes.data, loops_a.ctypes.data, int(n_noise), int(T),
+                                             int(spatial_volume), corr.ctypes.data, _stream(stream)))
+
+
+def disconnected_correlator(loops_b, loops_a, spatial_volume, stream=None):
+    """D(dt) of two per-noise loop sets (complex [n_noise][T] each), over distinct noise pairs;
+    returns complex [T]."""
+    lb = np.ascontiguousarray(np.stack([np.real(loops_b), np.imag(loops_b)], axis=-1), dtype=np.float64)
+    la = np.ascontiguousarray(np.stack([np.real(loops_a), np.imag(loops_a)], axis=-1), dtype=np.float64)
+    if lb.shape != la.shape or lb.ndim != 3:
+        raise ValueError("loops_b and loops_a must both be [n_noise][T] complex")
+    n, T = lb.shape[0], lb.shape[1]
+    out = np.zeros((T, 2), dtype=np.float64)
+    dl_disconnected_correlator(lb, la, n, T, spatial_volume, out, stream)
+    return out[:, 0] + 1j * out[:, 1]
 
 
 def dl_profile_config(kind: int):

@@ -1569,6 +1569,32 @@ extern "C" int dl_batch_loops(int32_t n_lat, const dl_gauge *gauges, const doubl
     });
 }
 
+// ====================================================================== correlator
+
+extern "C" int dl_disconnected_correlator(const double *loops_b, const double *loops_a, int32_t n_noise, int32_t T,
+                                          int64_t spatial_volume, double *corr, void *stream)
+{
+    return guarded([&]() {
+        DL_REQUIRE(loops_b && loops_a && corr, "dl_disconnected_correlator: null pointer");
+        DL_REQUIRE(n_noise >= 2, "dl_disconnected_correlator: needs at least two noises");
+        DL_REQUIRE(T >= 1 && T <= 65535, "dl_disconnected_correlator: T must be in [1, 65535]");
+        DL_REQUIRE(spatial_volume >= 1, "dl_disconnected_correlator: spatial volume must be positive");
+        DL_REQUIRE((int64_t)n_noise * T <= ((int64_t)1 << 28), "dl_disconnected_correlator: input too large");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const size_t nb = sizeof(double) * 2 * (size_t)n_noise * T, tb = sizeof(double) * 2 * (size_t)T;
+        DevBuf db(nb), da(nb), dsb(tb), dsa(tb), dout(tb);
+        DL_HIP(hipMemcpyAsync(db.p, loops_b, nb, hipMemcpyHostToDevice, s));
+        DL_HIP(hipMemcpyAsync(da.p, loops_a, nb, hipMemcpyHostToDevice, s));
+        const double norm = 1.0 / ((double)n_noise * (n_noise - 1)) / ((double)spatial_volume * T);
+        k_correlator(db.as<double>(), da.as<double>(), dsb.as<double>(), dsa.as<double>(), n_noise, T, norm,
+                     dout.as<double>(), s);
+        DL_HIP(hipGetLastError());
+        DL_HIP(hipMemcpyAsync(corr, dout.p, tb, hipMemcpyDeviceToHost, s));
+        DL_HIP(hipStreamSynchronize(s));
+        return DL_OK;
+    });
+}
+
 // ====================================================================== profiling API
 
 extern "C" int dl_profile_enable(int32_t on)

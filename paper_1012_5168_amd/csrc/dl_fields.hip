@@ -186,6 +186,51 @@ __global__ void gamma_contract_kernel(const double *C, int ncls, int T, const do
 }
 
 
+// Disconnected two-loop correlator (Section 3, Eq. 2) from per-noise loops
+// l[n][T] complex (re, im interleaved).  noise_sum_kernel: sum[t] = sum_n l[n][t]
+// (one thread per t, n in order).  corr_kernel, block dt: the ordered pairs of
+// distinct noises, as all pairs minus the same-noise ones,
+//     S = sum_t sb[t] sa[t + dt] - sum_n sum_t lb[n][t] la[n][t + dt]   (t + dt mod T),
+// and out[dt] = -norm * S.  Fixed summation order: deterministic.
+__global__ void noise_sum_kernel(const double *l, int n, int T, double *sum)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    double re = 0, im = 0;
+    for (int k = 0; k < n; ++k) {
+        re += l[((int64_t)k * T + t) * 2];
+        im += l[((int64_t)k * T + t) * 2 + 1];
+    }
+    sum[2 * t] = re;
+    sum[2 * t + 1] = im;
+}
+
+__global__ __launch_bounds__(256) void corr_kernel(const double *lb, const double *la, const double *sb,
+                                                   const double *sa, int n, int T, double norm, double *out)
+{
+    __shared__ double red[2 * 4];
+    const int dt = blockIdx.x;
+    double v[2] = {0.0, 0.0};
+    for (int k = threadIdx.x; k < n; k += blockDim.x)
+        for (int t = 0; t < T; ++t) {
+            const int u = t + dt < T ? t + dt : t + dt - T;
+            const double br = lb[((int64_t)k * T + t) * 2], bi = lb[((int64_t)k * T + t) * 2 + 1];
+            const double ar = la[((int64_t)k * T + u) * 2], ai = la[((int64_t)k * T + u) * 2 + 1];
+            v[0] += br * ar - bi * ai;
+            v[1] += br * ai + bi * ar;
+        }
+    block_sum<2>(v, red);
+    if (threadIdx.x != 0) return;
+    double cr = 0, ci = 0;
+    for (int t = 0; t < T; ++t) {
+        const int u = t + dt < T ? t + dt : t + dt - T;
+        cr += sb[2 * t] * sa[2 * u] - sb[2 * t + 1] * sa[2 * u + 1];
+        ci += sb[2 * t] * sa[2 * u + 1] + sb[2 * t + 1] * sa[2 * u];
+    }
+    out[2 * dt] = -norm * (cr - v[0]);
+    out[2 * dt + 1] = -norm * (ci - v[1]);
+}
+
 // dst(x) = A_{n,t(x)} eta(x): the source gamma5 sum_g W[n][g][t] Gamma_g^+ eta of
 // the adjoint solve of noise n, with A as [noise][T][4][4] complex (row a, column b)
 __global__ __launch_bounds__(BS) void adjoint_source_kernel(Field dst, int parity, SourceSpec src, Geom g,
@@ -371,6 +416,14 @@ void k_gamma_contract(const double *C, int n_noise, int ncls, int T, const doubl
                       int n_gamma, double *loops, hipStream_t s)
 {
     hipLaunchKernelGGL(gamma_contract_kernel, dim3(n_noise), dim3(128), 0, s, C, ncls, T, gam, gidx, n_gamma, loops);
+}
+
+void k_correlator(const double *lb, const double *la, double *sb, double *sa, int n, int T, double norm, double *out,
+                  hipStream_t s)
+{
+    hipLaunchKernelGGL(noise_sum_kernel, dim3((T + 63) / 64), dim3(64), 0, s, lb, n, T, sb);
+    hipLaunchKernelGGL(noise_sum_kernel, dim3((T + 63) / 64), dim3(64), 0, s, la, n, T, sa);
+    hipLaunchKernelGGL(corr_kernel, dim3(T), dim3(256), 0, s, lb, la, sb, sa, n, T, norm, out);
 }
 
 void k_adjoint_source(Field dst, int parity, const SourceSpec &src, const Geom &g, int nrhs, const double *A,

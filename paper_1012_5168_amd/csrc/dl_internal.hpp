@@ -270,6 +270,9 @@ void k_source(int prec, Field dst, int parity, const SourceSpec &src, const Geom
 void k_trace(int prec, Field se, Field so, const SourceSpec &src, const Geom &g, int nrhs, double *C,
              hipStream_t s);
 // loops[n][g][t] = sum_{d} sum_{ab} Gamma_g[a][b] C[n*ncls + d][t][a][b]
+// disconnected correlator: out[dt] = -norm * sum over distinct noise pairs (sb, sa: [T] complex scratch)
+void k_correlator(const double *lb, const double *la, double *sb, double *sa, int n, int T, double norm, double *out,
+                  hipStream_t s);
 void k_gamma_contract(const double *C, int n_noise, int ncls, int T, const double *gam, const int *gidx,
                       int n_gamma, double *loops, hipStream_t s);
 // adjoint source dst(x) = A[noise - first_noise][t(x)] eta(x), A as [noise][T][4][4] complex (FP64 field)

@@ -74,6 +74,22 @@ def test_null_handles_rejected(dl):
     assert lib.dl_profile_read(7, None, None) == dl.DL_EINVAL
 
 
+def test_correlator_arguments_rejected_before_device_work(dl):
+    """Too few noises, an empty time extent, a non-positive volume or a null pointer return
+    DL_EINVAL without touching the GPU."""
+    import numpy as np
+
+    lib = dl.load()
+    lb = np.zeros((3, 4, 2))
+    out = np.zeros((4, 2))
+    p, o = lb.ctypes.data, out.ctypes.data
+    assert lib.dl_disconnected_correlator(p, p, 1, 4, 8, o, None) == dl.DL_EINVAL
+    assert lib.dl_disconnected_correlator(p, p, 3, 0, 8, o, None) == dl.DL_EINVAL
+    assert lib.dl_disconnected_correlator(p, p, 3, 4, 0, o, None) == dl.DL_EINVAL
+    assert lib.dl_disconnected_correlator(None, p, 3, 4, 8, o, None) == dl.DL_EINVAL
+    assert lib.dl_disconnected_correlator(p, p, 3, 4, 8, None, None) == dl.DL_EINVAL
+
+
 def test_product_never_reaches_the_oracle():
     pkg = os.path.join(ROOT, "paper_1012_5168_amd")
     for dirpath, _, files in os.walk(pkg):
