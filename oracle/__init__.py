@@ -73,6 +73,7 @@ def lib():
             "or_z2_source": (None, [P, u64, i64, i32, i32, P]),
             "or_dilution_class": (i32, [P, i32, i64, i32, i32]),
             "or_dilution_count": (i32, [i32]),
+            "or_dilution_valid": (i32, [i32]),
             "or_loops_accumulate": (None, [P, P, P, i32, P, P]),
             "or_link_grad_accumulate": (None, [P, i32, f64, P, P, P]),
             "or_gamma5": (None, [P, P]),
@@ -178,6 +179,11 @@ def splitmix64(seed: int, counter: int) -> int:
 
 
 SCHEME_NONE, SCHEME_SPIN_COLOUR, SCHEME_CUBIC, SCHEME_EVEN_ODD = 0, 1, 2, 4
+SCHEME_COLOUR, SCHEME_SPIN, SCHEME_SPIN_EVEN_ODD, SCHEME_TIME = 8, 16, 32, 64
+
+
+def dilution_valid(scheme: int) -> bool:
+    return bool(lib().or_dilution_valid(int(scheme)))
 
 
 def dilution_count(scheme: int) -> int:
@@ -220,7 +226,7 @@ def loops_accumulate(dims, eta, s, gammas, out=None) -> np.ndarray:
 def _sources(dims, seed, noise, scheme):
     nd = dilution_count(scheme)
     for d in range(nd):
-        yield z2_source(dims, seed, noise, scheme, d if scheme else -1)
+        yield z2_source(dims, seed, noise, scheme, d if nd > 1 else -1)
 
 
 def loops_point(U, dims, kappa, site, gammas, tol=1e-13, tap=1):

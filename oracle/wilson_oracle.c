@@ -455,18 +455,37 @@ static cplx z2_entry(uint64_t seed, int64_t V, int64_t noise, int64_t site, int 
 
 /*
  * Dilution class of entry (site, spin, colour) under a scheme (Section 2):
- *   scheme bit 0: spin-colour dilution, class d_sc = 3*spin + colour (12);
- *   scheme bit 1: cubic spatial dilution, class c = (x&1) + 2(y&1) + 4(z&1) (8);
- *   scheme bit 2: spatial even-odd dilution, class (x+y+z+t)&1 (2).
- * Classes of the enabled factors combine in that order, each later factor
- * being the faster-running digit: d = (d_sc*8 + c)*2 + eo.
+ *   scheme bit 0 (1): spin-colour dilution, class 3*spin + colour (12);
+ *   scheme bit 4 (16): spin dilution, class spin (4);
+ *   scheme bit 5 (32): spin even-odd partitioning, class spin & 1 (2);
+ *   scheme bit 3 (8): colour dilution, class colour (3);
+ *   scheme bit 1 (2): cubic spatial dilution, class (x&1) + 2(y&1) + 4(z&1) (8);
+ *   scheme bit 2 (4): spatial even-odd dilution, class (x+y+z+t)&1 (2).
+ * Classes of the enabled factors combine in the order listed, each later
+ * factor being the faster-running digit, so spin + colour (16 | 8) gives the
+ * same classes as spin-colour (1).  Bit 0 excludes bits 3-5; bits 4 and 5
+ * exclude each other (or_dilution_valid).
+ *   scheme bit 6 (64): time dilution, one class: noise n is supported on
+ * timeslice n mod T only (or_z2_source), so every noise costs the same
+ * number of solves and the timeslices are covered across noises.
  */
+int32_t or_dilution_valid(int32_t scheme)
+{
+    if (scheme < 0 || scheme > 127) return 0;
+    if ((scheme & 1) && (scheme & (8 | 16 | 32))) return 0;
+    if ((scheme & 16) && (scheme & 32)) return 0;
+    return 1;
+}
+
 int32_t or_dilution_class(const int32_t *L, int32_t scheme, int64_t site, int32_t spin, int32_t col)
 {
     int c[4];
     coords(L, site, c);
     int32_t d = 0;
     if (scheme & 1) d = d * 12 + 3 * spin + col;
+    if (scheme & 16) d = d * 4 + spin;
+    if (scheme & 32) d = d * 2 + (spin & 1);
+    if (scheme & 8) d = d * 3 + col;
     if (scheme & 2) d = d * 8 + (c[0] & 1) + 2 * (c[1] & 1) + 4 * (c[2] & 1);
     if (scheme & 4) d = d * 2 + ((c[0] + c[1] + c[2] + c[3]) & 1);
     return d;
@@ -474,22 +493,29 @@ int32_t or_dilution_class(const int32_t *L, int32_t scheme, int64_t site, int32_
 
 int32_t or_dilution_count(int32_t scheme)
 {
-    return ((scheme & 1) ? 12 : 1) * ((scheme & 2) ? 8 : 1) * ((scheme & 4) ? 2 : 1);
+    return ((scheme & 1) ? 12 : 1) * ((scheme & 16) ? 4 : 1) * ((scheme & 32) ? 2 : 1) * ((scheme & 8) ? 3 : 1) *
+           ((scheme & 2) ? 8 : 1) * ((scheme & 4) ? 2 : 1);
 }
 
-/* eta_{noise,d}: the noise vector masked to dilution class d (d = -1: no mask) */
+/* eta_{noise,d}: the noise vector masked to dilution class d (d = -1: no class
+ * mask); under time dilution also masked to timeslice noise mod T */
 void or_z2_source(const int32_t *L, uint64_t seed, int64_t noise, int32_t scheme, int32_t d, double *out)
 {
     const int64_t V = volume(L);
     cplx *eta = (cplx *)out;
+    const int tsrc = (int)(noise % L[3]);
 #pragma omp parallel for schedule(static) if (V >= 1024)
-    for (int64_t i = 0; i < V; ++i)
+    for (int64_t i = 0; i < V; ++i) {
+        int c[4];
+        coords(L, i, c);
         for (int al = 0; al < 4; ++al)
             for (int a = 0; a < 3; ++a) {
                 cplx v = z2_entry(seed, V, noise, i, al, a);
                 if (d >= 0 && or_dilution_class(L, scheme, i, al, a) != d) v = 0;
+                if ((scheme & 64) && c[3] != tsrc) v = 0;
                 eta[(i * 4 + al) * 3 + a] = v;
             }
+    }
 }
 
 /* ------------------------------------------------------------------ */

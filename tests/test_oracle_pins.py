@@ -17,7 +17,12 @@ that does not share its code:
   of Tr[Gamma M^-1(x,x)], gauge invariance of exact loops.
 * Noise and dilution: every entry in {(+-1 +-i)/sqrt 2}, phase balance,
   unbiasedness and the closed-form variance sum_{i!=j} |A_ij|^2 of the complex
-  Z2 trace estimator, dilution classes against coordinates computed here.
+  Z2 trace estimator, dilution classes against coordinates computed here; for
+  every valid scheme the diluted pieces partition the noise and each piece is
+  supported where its class says (spin / colour / spin parity slices, cubic
+  vertices, site parity, and the one timeslice noise mod T of time dilution,
+  all sliced with numpy); the diluted estimator's expectation is the exact
+  trace and its variance the closed form restricted to same-class pairs.
 * Truncated solver method: exact when the low-precision solve is exact,
   unbiased (z-test against the dense exact answer).
 * Derivatives: d/dkappa against central differences with identical noise and
@@ -559,4 +564,109 @@ def test_correlator_swap_symmetry():
     dab = oracle.disconnected_correlator(la, lb, L3)
     for dt in range(T):
         assert abs(dba[dt] - dab[(T - dt) % T]) < 1e-14 * np.max(np.abs(dba))
+
+
+VALID_SCHEMES = [s for s in range(128) if oracle.dilution_valid(s)]
+
+
+def test_dilution_scheme_validity():
+    """Spin-colour excludes the separate spin / spin-parity / colour factors; spin and spin parity
+    exclude each other; everything else combines."""
+    for s in range(128):
+        bad = bool(s & 1 and s & (8 | 16 | 32)) or bool(s & 16 and s & 32)
+        assert oracle.dilution_valid(s) == (not bad), s
+    assert not oracle.dilution_valid(128) and not oracle.dilution_valid(-1)
+    assert len(VALID_SCHEMES) == 2 * 2 * 2 * (1 + 2 * 3)  # time x cubic x site-parity x spin/colour options
+
+
+@pytest.mark.parametrize("scheme", [s for s in VALID_SCHEMES if s & (8 | 16 | 32 | 64)])
+def test_new_dilution_pieces_partition_and_support(scheme):
+    dims = (4, 2, 2, 6)
+    X, Y, Z, T = dims
+    cs = coords_of(dims)
+    noise = 11
+    eta = oracle.z2_source(dims, 31, noise)  # whole noise vector, no masks at all
+    if scheme & 64:
+        eta = eta * (cs[:, 3] == noise % T)[:, None, None]
+    nd = oracle.dilution_count(scheme)
+    parts = [oracle.z2_source(dims, 31, noise, scheme, d if nd > 1 else -1) for d in range(nd)]
+    assert np.array_equal(np.sum(parts, axis=0), eta)
+    assert np.all(np.sum([np.abs(p) > 0 for p in parts], axis=0) == (np.abs(eta) > 0))
+    # digits of d, slowest first, in the order spin-colour | spin | spin parity | colour | cubic | parity
+    radices = []
+    if scheme & 1:
+        radices.append(("sc", 12))
+    if scheme & 16:
+        radices.append(("spin", 4))
+    if scheme & 32:
+        radices.append(("spar", 2))
+    if scheme & 8:
+        radices.append(("col", 3))
+    if scheme & 2:
+        radices.append(("cub", 8))
+    if scheme & 4:
+        radices.append(("eo", 2))
+    spin = np.arange(4)[None, :, None]
+    col = np.arange(3)[None, None, :]
+    cub = ((cs[:, 0] & 1) + 2 * (cs[:, 1] & 1) + 4 * (cs[:, 2] & 1))[:, None, None]
+    eo = (cs.sum(axis=1) & 1)[:, None, None]
+    for d in range(nd):
+        rem, digit = d, {}
+        for name, r in reversed(radices):
+            digit[name] = rem % r
+            rem //= r
+        allowed = np.ones((len(cs), 4, 3), bool)
+        if "sc" in digit:
+            allowed &= (3 * spin + col) == digit["sc"]
+        if "spin" in digit:
+            allowed &= spin == digit["spin"]
+        if "spar" in digit:
+            allowed &= (spin % 2) == digit["spar"]
+        if "col" in digit:
+            allowed &= col == digit["col"]
+        if "cub" in digit:
+            allowed &= cub == digit["cub"]
+        if "eo" in digit:
+            allowed &= eo == digit["eo"]
+        assert np.array_equal(parts[d], np.where(allowed, eta, 0)), (scheme, d)
+
+
+def test_spin_and_colour_equal_spin_colour():
+    dims = (2, 2, 2, 4)
+    for d in range(12):
+        assert np.array_equal(oracle.z2_source(dims, 5, 2, 16 | 8, d), oracle.z2_source(dims, 5, 2, 1, d))
+
+
+@pytest.mark.parametrize("scheme", [32, 8, 32 | 8, 64, 64 | 16, 4 | 32])
+def test_new_dilution_estimators_unbiased_with_closed_form_variance(scheme):
+    """eta^+ A eta summed over the classes of one noise: mean Tr[A restricted to the support],
+    variance sum over same-class off-diagonal pairs |A_ij|^2 (complex Z2 entries: E[e_i* e_j] =
+    delta_ij, E|e_i|^2 |e_j|^2 = 1, E[e_i*^2 e_j^2] = 0).  For time dilution the support of noise n
+    is the timeslice n mod T, so the estimate is of the trace over that timeslice."""
+    dims = (2, 2, 2, 2)
+    n = 192
+    rng = np.random.default_rng(80 + scheme)
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    nd = oracle.dilution_count(scheme)
+    cls = np.array([oracle.dilution_class(dims, scheme, i // 12, (i // 3) % 4, i % 3) for i in range(n)])
+    tsl = coords_of(dims)[np.arange(n) // 12, 3]
+    N = 2400
+    for parity_t in ([0, 1] if scheme & 64 else [None]):
+        noises = [k for k in range(N) if parity_t is None or k % 2 == parity_t]
+        sup = np.ones(n, bool) if parity_t is None else (tsl == parity_t)
+        est = []
+        for k in noises:
+            tot = 0j
+            for d in range(nd):
+                e = oracle.z2_source(dims, 77, k, scheme, d if nd > 1 else -1).reshape(-1)
+                tot += np.vdot(e, A @ e)
+            est.append(tot)
+        est = np.array(est)
+        same = (cls[:, None] == cls[None, :]) & sup[:, None] & sup[None, :]
+        np.fill_diagonal(same, False)
+        var_closed = np.sum(np.abs(A[same]) ** 2)
+        exact = np.sum(np.diag(A)[sup])
+        assert abs(est.mean() - exact) < 4.5 * np.sqrt(var_closed / len(est)), (scheme, parity_t)
+        var_emp = np.mean(np.abs(est - exact) ** 2)
+        assert abs(var_emp / var_closed - 1) < 5 * np.sqrt(2.0 / len(est)) + 0.03, (scheme, var_emp / var_closed)
 
