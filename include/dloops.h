@@ -32,9 +32,15 @@
  *     Flood 2014) seeded with `seed`; bit 0 gives the sign of the real part and
  *     bit 1 that of the imaginary part (0 -> +), amplitude 1/sqrt(2);
  *   - dilution (Section 2) scheme bits: 1 = spin-colour (12 classes,
- *     d = 3 s + c), 2 = cubic spatial (8 classes, (x&1) + 2(y&1) + 4(z&1)),
- *     4 = spatial even-odd (2 classes, (x+y+z+t)&1); enabled factors combine
- *     in that order, the later factor running fastest.
+ *     d = 3 s + c), 16 = spin (4 classes, s), 32 = spin even-odd
+ *     partitioning (2 classes, s & 1), 8 = colour (3 classes, c), 2 = cubic
+ *     spatial (8 classes, (x&1) + 2(y&1) + 4(z&1)), 4 = spatial even-odd
+ *     (2 classes, (x+y+z+t)&1); enabled factors combine in that order, the
+ *     later factor running fastest (so 16 | 8 gives the classes of 1).  Bit 1
+ *     excludes 8, 16 and 32; 16 and 32 exclude each other.  64 = time
+ *     dilution: noise n is supported on timeslice n mod T only (no extra
+ *     classes; its loops are zero on the other timeslices, and the noises
+ *     cover the timeslices in turn).
  *
  * Every call returns a dl_status.  On failure dl_last_error() describes it
  * (thread-local text, valid until the next call on the same thread).
@@ -87,7 +93,15 @@ typedef enum { DL_BICGSTAB = 0, DL_CGNR = 1 } dl_solver;
 
 typedef enum { DL_SRC_Z2 = 0, DL_SRC_POINT = 1 } dl_source_kind;
 
-typedef enum { DL_DIL_SPIN_COLOUR = 1, DL_DIL_CUBIC = 2, DL_DIL_EVEN_ODD = 4 } dl_dilution_bits;
+typedef enum {
+    DL_DIL_SPIN_COLOUR = 1,
+    DL_DIL_CUBIC = 2,
+    DL_DIL_EVEN_ODD = 4,
+    DL_DIL_COLOUR = 8,
+    DL_DIL_SPIN = 16,
+    DL_DIL_SPIN_EVEN_ODD = 32,
+    DL_DIL_TIME = 64
+} dl_dilution_bits;
 
 typedef struct dl_lattice_s *dl_lattice;
 typedef struct dl_gauge_s *dl_gauge;

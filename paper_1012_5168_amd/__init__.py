@@ -27,6 +27,7 @@ DL_OP_DHOP, DL_OP_M, DL_OP_MDAG, DL_OP_MHAT, DL_OP_MHATDAG, DL_OP_DHOPDAG = 0, 1
 DL_BICGSTAB, DL_CGNR = 0, 1
 DL_SRC_Z2, DL_SRC_POINT = 0, 1
 DL_DIL_SPIN_COLOUR, DL_DIL_CUBIC, DL_DIL_EVEN_ODD = 1, 2, 4
+DL_DIL_COLOUR, DL_DIL_SPIN, DL_DIL_SPIN_EVEN_ODD, DL_DIL_TIME = 8, 16, 32, 64
 
 _STATUS = {
     DL_EINVAL: "DL_EINVAL",

@@ -1105,8 +1105,9 @@ namespace {
 
 int dilution_classes(int scheme)
 {
-    return ((scheme & DL_DIL_SPIN_COLOUR) ? 12 : 1) * ((scheme & DL_DIL_CUBIC) ? 8 : 1) *
-           ((scheme & DL_DIL_EVEN_ODD) ? 2 : 1);
+    return ((scheme & DL_DIL_SPIN_COLOUR) ? 12 : 1) * ((scheme & DL_DIL_SPIN) ? 4 : 1) *
+           ((scheme & DL_DIL_SPIN_EVEN_ODD) ? 2 : 1) * ((scheme & DL_DIL_COLOUR) ? 3 : 1) *
+           ((scheme & DL_DIL_CUBIC) ? 8 : 1) * ((scheme & DL_DIL_EVEN_ODD) ? 2 : 1);
 }
 
 void validate_sources(const dl_lattice_s &lat, const dl_sources *src)
@@ -1119,7 +1120,12 @@ void validate_sources(const dl_lattice_s &lat, const dl_sources *src)
     } else {
         DL_REQUIRE(src->n_noise >= 1, "sources: n_noise must be >= 1");
         DL_REQUIRE(src->first_noise >= 0, "sources: first_noise must be >= 0");
-        DL_REQUIRE((src->scheme & ~7) == 0, "sources: unknown dilution bits");
+        DL_REQUIRE((src->scheme & ~127) == 0, "sources: unknown dilution bits");
+        DL_REQUIRE(!((src->scheme & DL_DIL_SPIN_COLOUR) &&
+                     (src->scheme & (DL_DIL_COLOUR | DL_DIL_SPIN | DL_DIL_SPIN_EVEN_ODD))),
+                   "sources: spin-colour dilution excludes the separate spin and colour factors");
+        DL_REQUIRE(!((src->scheme & DL_DIL_SPIN) && (src->scheme & DL_DIL_SPIN_EVEN_ODD)),
+                   "sources: spin dilution and spin even-odd partitioning exclude each other");
     }
 }
 
@@ -1166,6 +1172,7 @@ extern "C" int dl_sources_fill(dl_lattice lat, const dl_sources *src, int64_t fi
         ss.scheme = src->kind == DL_SRC_POINT ? 0 : src->scheme;
         ss.seed = src->seed;
         ss.V = lat->V;
+        ss.T = lat->dims[3];
         ss.point_site = src->point_site;
         ss.noise = dnoise.as<int64_t>();
         ss.cls = dcls.as<int>();
@@ -1273,6 +1280,7 @@ int loops_run(dl_gauge G, double kappa, const dl_sources *src, const dl_solve_pa
         ss.scheme = src->kind == DL_SRC_POINT ? 0 : src->scheme;
         ss.seed = src->seed;
         ss.V = V;
+        ss.T = T;
         ss.point_site = src->point_site;
         ss.noise = dnoise.as<int64_t>();
         ss.cls = dcls.as<int>();
@@ -1526,6 +1534,7 @@ extern "C" int dl_batch_loops(int32_t n_lat, const dl_gauge *gauges, const doubl
                 ss.scheme = srcs[l].kind == DL_SRC_POINT ? 0 : srcs[l].scheme;
                 ss.seed = srcs[l].seed;
                 ss.V = G->lat.V;
+                ss.T = G->lat.dims[3];
                 ss.point_site = srcs[l].point_site;
                 ss.noise = dnoise.back().as<int64_t>();
                 ss.cls = dcls.back().as<int>();

@@ -34,6 +34,9 @@ __device__ __forceinline__ int dil_class(int scheme, const Site &s, int spin, in
 {
     int d = 0;
     if (scheme & DL_DIL_SPIN_COLOUR) d = d * 12 + 3 * spin + col;
+    if (scheme & DL_DIL_SPIN) d = d * 4 + spin;
+    if (scheme & DL_DIL_SPIN_EVEN_ODD) d = d * 2 + (spin & 1);
+    if (scheme & DL_DIL_COLOUR) d = d * 3 + col;
     if (scheme & DL_DIL_CUBIC) d = d * 8 + (s.x & 1) + 2 * (s.y & 1) + 4 * (s.z & 1);
     if (scheme & DL_DIL_EVEN_ODD) d = d * 2 + ((s.x + s.y + s.z + s.t) & 1);
     return d;
@@ -50,6 +53,11 @@ __device__ __forceinline__ void source_site(const SourceSpec &src, int rhs, cons
         return;
     }
     const double amp = 0.70710678118654752440;  // 1/sqrt(2)
+    if ((src.scheme & DL_DIL_TIME) && st.t != (int)(src.noise[rhs] % src.T)) {
+#pragma unroll
+        for (int e = 0; e < 12; ++e) eta[e] = {0.0, 0.0};
+        return;
+    }
     const uint64_t base = ((uint64_t)src.noise[rhs] * (uint64_t)src.V + (uint64_t)lex) * 12ull;
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)

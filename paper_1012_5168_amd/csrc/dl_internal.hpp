@@ -261,6 +261,7 @@ struct SourceSpec {
     int scheme;       // dilution bits
     uint64_t seed;
     int64_t V;
+    int T;            // time extent (time dilution: noise n lives on timeslice n mod T)
     int point_site;
     const int64_t *noise;  // [nrhs] noise number of each right-hand side (device)
     const int *cls;        // [nrhs] dilution class (device); point: 3*spin + colour

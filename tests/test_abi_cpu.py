@@ -56,7 +56,12 @@ def test_sources_count_and_validation(dl):
     assert dl.dl_sources_count(h, dl.z2_sources(1, 24, scheme=dl.DL_DIL_SPIN_COLOUR)) == 288
     assert dl.dl_sources_count(h, dl.z2_sources(1, 8, scheme=dl.DL_DIL_SPIN_COLOUR | dl.DL_DIL_CUBIC)) == 768
     assert dl.dl_sources_count(h, dl.point_sources(0)) == 12
-    for bad in [dl.z2_sources(1, 0), dl.z2_sources(1, 2, scheme=8), dl.point_sources(256),
+    assert dl.dl_sources_count(h, dl.z2_sources(1, 3, scheme=dl.DL_DIL_SPIN | dl.DL_DIL_COLOUR)) == 36
+    assert dl.dl_sources_count(h, dl.z2_sources(1, 3, scheme=dl.DL_DIL_SPIN_EVEN_ODD | dl.DL_DIL_CUBIC)) == 48
+    assert dl.dl_sources_count(h, dl.z2_sources(1, 5, scheme=dl.DL_DIL_TIME)) == 5
+    for bad in [dl.z2_sources(1, 0), dl.z2_sources(1, 2, scheme=128), dl.point_sources(256),
+                dl.z2_sources(1, 2, scheme=dl.DL_DIL_SPIN_COLOUR | dl.DL_DIL_COLOUR),
+                dl.z2_sources(1, 2, scheme=dl.DL_DIL_SPIN | dl.DL_DIL_SPIN_EVEN_ODD),
                 dl.dl_sources(dl.DL_SRC_POINT, 0, 0, 0, 2, 0), dl.dl_sources(7, 0, 0, 0, 1, 0)]:
         with pytest.raises(dl.DLError) as e:
             dl.dl_sources_count(h, bad)
