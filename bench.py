@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--copy-reference", action="store_true",
                     help="first run a plain device copy (2 GiB read, 2 GiB written), the reference for hardware byte counters")
     ap.add_argument("--cpu-only", action="store_true", help="time only the CPU oracle sample")
+    ap.add_argument("--dilution-study", action="store_true",
+                    help="instead of the timed step: error of the time-averaged loop versus the number of "
+                         "inversions for several dilution schemes (Gamma = 1, gamma5, gamma1 gamma3)")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the per-precision hopping-kernel sweep and the single-right-hand-side figures")
     return ap.parse_args()
@@ -185,6 +188,48 @@ def dslash_sweep(dl, torch, G, copy_gbs):
     return out
 
 
+def dilution_study(dl, G, w, n_noise=16):
+    """The error-versus-inversions comparison of dilution schemes (Section 4, on the synthetic field):
+    for each scheme, n_noise noises give per-noise estimates e_n of the time-averaged loop
+    (1/T) sum_t L_Gamma(t) (under time dilution a noise sees one timeslice, so e_n = L_Gamma(t_n));
+    the error after N noises is sigma / sqrt(N) at N_inv = N x (solves per noise).  `vs_optimal` is
+    sigma sqrt(solves per noise) / sigma_undiluted: the scheme's error at equal N_inv relative to the
+    1/sqrt(N_inv) extrapolation from the undiluted estimator (below 1: dilution pays)."""
+    import numpy as np
+
+    T = w["dims"][3]
+    gam = {"1": 0, "gamma5": 15, "gamma1gamma3": 5}
+    schemes = {"none": 0, "time": dl.DL_DIL_TIME, "colour": dl.DL_DIL_COLOUR, "spin": dl.DL_DIL_SPIN,
+               "spin_even_odd": dl.DL_DIL_SPIN_EVEN_ODD, "spin_colour": dl.DL_DIL_SPIN_COLOUR,
+               "spin_colour_time": dl.DL_DIL_SPIN_COLOUR | dl.DL_DIL_TIME,
+               "spin_colour_even_odd": dl.DL_DIL_SPIN_COLOUR | dl.DL_DIL_EVEN_ODD,
+               "spin_colour_cubic": dl.DL_DIL_SPIN_COLOUR | dl.DL_DIL_CUBIC}
+    prm = dl.solve_params(tol=1e-10, maxiter=1000)
+    res, sig0 = {}, {}
+    for name, sch in schemes.items():
+        src = dl.z2_sources(w["noise_seed"] + 500, n_noise, scheme=sch)
+        per = dl.dl_sources_count(G.lattice.h, src) // n_noise
+        t0 = time.perf_counter()
+        L, st = dl.loops(G, w["kappa"], src, list(gam.values()), prm)
+        secs = time.perf_counter() - t0
+        assert all(x[0] == dl.DL_OK for x in st), name
+        if sch & dl.DL_DIL_TIME:
+            e = np.array([L[n][:, n % T] for n in range(n_noise)])  # [noise][gamma]
+        else:
+            e = L.mean(axis=2)
+        out = {"solves_per_noise": per, "seconds": round(secs, 3)}
+        for k, g in enumerate(gam):
+            sigma = float(np.sqrt(np.mean(np.abs(e[:, k] - e[:, k].mean()) ** 2) * n_noise / (n_noise - 1)))
+            if name == "none":
+                sig0[g] = sigma
+            out[g] = {"sigma_per_noise": sigma, "mean": [float(e[:, k].mean().real), float(e[:, k].mean().imag)],
+                      "error_at_n_inv": [[per * m, sigma / np.sqrt(m)] for m in (1, 2, 4, 8, n_noise)],
+                      "vs_optimal": sigma * np.sqrt(per) / sig0[g]}
+        res[name] = out
+    return {"study": "error of the time-averaged loop versus inversions per dilution scheme",
+            "lattice": list(w["dims"]), "kappa": w["kappa"], "n_noise": n_noise, "schemes": res}
+
+
 def synth_workload(name):
     import synth
 
@@ -237,6 +282,9 @@ def main():
     lat = dl.Lattice(dims, 1)
     G = dl.Gauge(lat, U, precs=(dl.DL_F64, dl.DL_F32, dl.DL_F16, dl.DL_BF16), recon=12)
     stream = torch.cuda.current_stream()
+    if args.dilution_study:
+        print(json.dumps(dilution_study(dl, G, w)), flush=True)
+        return
     prm = dl.solve_params(tol=1e-10, maxiter=1000)
     gam = [0, 15]
     src = dl.z2_sources(w["noise_seed"], args.noises, scheme=dl.DL_DIL_SPIN_COLOUR)
