@@ -22,7 +22,10 @@ and adds the estimator drivers, each a direct transcription of the method:
 * :func:`loops_dkappa` and :func:`loops_link_grad` -- derivatives of the same
   estimators, from ``dM^-1/dkappa = M^-1 D M^-1`` and the adjoint solve;
 * :func:`disconnected_correlator` -- the two-loop (disconnected) correlator of
-  Section 3, Eq. (2), from per-noise loop estimates over distinct noise pairs.
+  Section 3, Eq. (2), from per-noise loop estimates over distinct noise pairs;
+* :func:`smear` and :func:`loops_z2_smeared` -- gauge-covariant Gaussian
+  smearing of quark fields (Section 2) and the loop of smeared fields,
+  estimated with the smeared noise xi = S eta at source and sink.
 
 Parity is pinned against closed forms, invariants and dense linear algebra in
 ``tests/test_oracle_pins.py``; the pins are listed in the header of that file.
@@ -74,6 +77,7 @@ def lib():
             "or_dilution_class": (i32, [P, i32, i64, i32, i32]),
             "or_dilution_count": (i32, [i32]),
             "or_dilution_valid": (i32, [i32]),
+            "or_smear": (None, [P, P, ctypes.c_double, i32, P, P]),
             "or_loops_accumulate": (None, [P, P, P, i32, P, P]),
             "or_link_grad_accumulate": (None, [P, i32, f64, P, P, P]),
             "or_gamma5": (None, [P, P]),
@@ -395,5 +399,25 @@ def disconnected_correlator(loops_b, loops_a, spatial_volume):
                 for t in range(T):
                     acc += lb[i, t] * la[j, (t + dt) % T]
         out[dt] = -acc / (n * (n - 1)) / (spatial_volume * T)
+    return out
+
+
+def smear(U, psi, dims, alpha, iters) -> np.ndarray:
+    """S psi = F^iters psi, F psi = [psi + alpha sum_i (U_i psi(x+i) + U_i(x-i)^+ psi(x-i))] / (1 + 6 alpha)."""
+    out = np.empty_like(_c128(psi))
+    lib().or_smear(_ptr(_dims(dims)), _ptr(_c128(U)), float(alpha), int(iters), _ptr(_c128(psi)), _ptr(out))
+    return out
+
+
+def loops_z2_smeared(U, dims, kappa, seed, noises, scheme, gammas, alpha, iters, tol=1e-13, tap=1):
+    """Per-noise loops of smeared quark fields, L^S_Gamma(t) = sum_{x in t} Tr[Gamma (S M^-1 S)(x,x)],
+    estimated as sum_d xi_d^+ P_t Gamma M^-1 xi_d with xi_d = S eta_d (S is hermitian and acts within
+    timeslices and trivially on spin, so it moves from the sink onto the noise).  [len(noises)][n_gamma][T]."""
+    out = np.zeros((len(noises), len(gammas), dims[3]), dtype=np.complex128)
+    for k, n in enumerate(noises):
+        for eta in _sources(dims, seed, n, scheme):
+            xi = smear(U, eta, dims, alpha, iters)
+            s, _, _ = solve(U, xi, dims, kappa, tol, tap=tap)
+            out[k] = loops_accumulate(dims, xi, s, gammas, out[k])
     return out
 

@@ -220,6 +220,54 @@ void or_dhop_dag(const int32_t *L, int32_t tap, const double *U, const double *i
     dhop_any(L, tap, (const cplx *)U, (const cplx *)in, (cplx *)out, 1);
 }
 
+/*
+ * Gauge-covariant Gaussian smearing of quark fields (Section 2; the paper
+ * names the method but gives no parameters), one step:
+ *   (F psi)(x) = [ psi(x) + alpha sum_{i = x,y,z} ( U_i(x) psi(x+i) + U_i(x-i)^+ psi(x-i) ) ] / (1 + 6 alpha),
+ * spin-diagonal, within each timeslice, periodic in space (no boundary sign).
+ * out = F^iters in.
+ */
+void or_smear(const int32_t *L, const double *Ud, double alpha, int32_t iters, const double *in_d, double *out_d)
+{
+    const int64_t V = volume(L);
+    const cplx *U = (const cplx *)Ud;
+    cplx *a = malloc(sizeof(cplx) * V * 12), *b = malloc(sizeof(cplx) * V * 12);
+    memcpy(a, in_d, sizeof(cplx) * V * 12);
+    const double norm = 1.0 / (1.0 + 6.0 * alpha);
+    for (int it = 0; it < iters; ++it) {
+#pragma omp parallel for schedule(static) if (V >= 1024)
+        for (int64_t i = 0; i < V; ++i) {
+            cplx acc[12];
+            for (int k = 0; k < 12; ++k) acc[k] = 0;
+            for (int mu = 0; mu < 3; ++mu)
+                for (int dir = -1; dir <= 1; dir += 2) {
+                    const int64_t j = hop(L, i, mu, dir);
+                    cplx W[3][3];
+                    if (dir > 0) {
+                        const cplx *u = U + (mu * V + i) * 9;
+                        for (int r = 0; r < 3; ++r)
+                            for (int q = 0; q < 3; ++q) W[r][q] = u[3 * r + q];
+                    } else {
+                        const cplx *u = U + (mu * V + j) * 9;
+                        for (int r = 0; r < 3; ++r)
+                            for (int q = 0; q < 3; ++q) W[r][q] = conj(u[3 * q + r]);
+                    }
+                    const cplx *p = a + j * 12;
+                    for (int sp = 0; sp < 4; ++sp)
+                        for (int r = 0; r < 3; ++r)
+                            for (int q = 0; q < 3; ++q) acc[3 * sp + r] += W[r][q] * p[3 * sp + q];
+                }
+            for (int k = 0; k < 12; ++k) b[i * 12 + k] = (a[i * 12 + k] + alpha * acc[k]) * norm;
+        }
+        cplx *t = a;
+        a = b;
+        b = t;
+    }
+    memcpy(out_d, a, sizeof(cplx) * V * 12);
+    free(a);
+    free(b);
+}
+
 /* out = M in = in - kappa D in  (dag selects M^dagger = 1 - kappa D^dagger) */
 static void apply_m(const int32_t *L, int tap, const cplx *U, double kappa, const cplx *in, cplx *out,
                     int dag)

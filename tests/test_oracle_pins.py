@@ -28,6 +28,12 @@ that does not share its code:
 * Derivatives: d/dkappa against central differences with identical noise and
   against the dense M^-1 D M^-1; the link gradient against directional
   central differences.
+* Smearing: free-field plane waves are eigenvectors with eigenvalue
+  [(1 + 2 alpha sum_i cos p_i) / (1 + 6 alpha)]^iters; gauge covariance;
+  hermiticity; a field on one timeslice and one spin stays there; the smeared
+  loop driver equals dense algebra (xi = S eta, s = M^-1 xi from numpy's
+  inverse), and the smeared estimator's mean is Tr[P_t Gamma S M^-1 S] (z-test,
+  S assembled column by column from the smearing of unit vectors).
 * Disconnected correlator (Eq. 2): identical per-noise estimates against the
   circular cross-correlation computed with numpy's FFT (convolution theorem);
   unbiasedness over distinct noise pairs when the two loops of one noise are
@@ -669,4 +675,94 @@ def test_new_dilution_estimators_unbiased_with_closed_form_variance(scheme):
         assert abs(est.mean() - exact) < 4.5 * np.sqrt(var_closed / len(est)), (scheme, parity_t)
         var_emp = np.mean(np.abs(est - exact) ** 2)
         assert abs(var_emp / var_closed - 1) < 5 * np.sqrt(2.0 / len(est)) + 0.03, (scheme, var_emp / var_closed)
+
+
+# ------------------------------------------------------------ smearing (Section 2)
+
+def test_smearing_free_field_plane_waves():
+    dims = (4, 6, 4, 3)
+    U = synth.unit_field(dims)
+    cs = coords_of(dims)
+    rng = np.random.default_rng(90)
+    alpha, iters = 0.7, 3
+    for n in [(0, 0, 0), (1, 2, 3), (2, 5, 1)]:
+        p = 2 * np.pi * np.array(n) / np.array(dims[:3])
+        chi = rng.normal(size=(4, 3)) + 1j * rng.normal(size=(4, 3))
+        f_t = rng.normal(size=dims[3]) + 1j * rng.normal(size=dims[3])  # any time dependence
+        psi = (np.exp(1j * cs[:, :3] @ p) * f_t[cs[:, 3]])[:, None, None] * chi[None]
+        lam = ((1 + 2 * alpha * np.cos(p).sum()) / (1 + 6 * alpha)) ** iters
+        got = oracle.smear(U, psi, dims, alpha, iters)
+        assert np.max(np.abs(got - lam * psi)) < 1e-13 * np.max(np.abs(psi)), n
+
+
+def test_smearing_gauge_covariant_hermitian_local():
+    dims = (4, 2, 4, 6)
+    V = int(np.prod(dims))
+    U = synth.gauge_field(dims, 0.7, seed=91)
+    Om = synth.random_su3(V, seed=92)
+    cs = coords_of(dims)
+    Up = np.empty_like(U)
+    for mu in range(4):
+        c2 = cs.copy()
+        c2[:, mu] = (c2[:, mu] + 1) % dims[mu]
+        nb = site_of(dims, c2.T)
+        Up[mu] = Om @ U[mu] @ np.conj(np.transpose(Om[nb], (0, 2, 1)))
+    phi, psi = synth.random_spinor(dims, 2, seed=93)
+    a, n = 0.45, 4
+    lhs = oracle.smear(Up, np.einsum("xab,xsb->xsa", Om, psi), dims, a, n)
+    rhs = np.einsum("xab,xsb->xsa", Om, oracle.smear(U, psi, dims, a, n))
+    assert np.max(np.abs(lhs - rhs)) < 1e-13
+    assert abs(np.vdot(phi, oracle.smear(U, psi, dims, a, n)) - np.vdot(oracle.smear(U, phi, dims, a, n), psi)) \
+        < 1e-12 * np.linalg.norm(phi) * np.linalg.norm(psi)
+    # a point source on spin 1 at one site of timeslice 2 spreads over that timeslice and spin only
+    one = np.zeros_like(psi)
+    site = site_of(dims, np.array([1, 0, 2, 2]))
+    one[site, 1, 0] = 1.0
+    sm = oracle.smear(U, one, dims, a, n)
+    sel = cs[:, 3] == 2
+    assert np.all(sm[~sel] == 0) and np.all(sm[:, [0, 2, 3], :] == 0)
+    assert np.count_nonzero(np.abs(sm[sel, 1, 0]) > 0) > 8
+
+
+def dense_smearing(U, dims, alpha, iters):
+    n = int(np.prod(dims)) * 12
+    S = np.zeros((n, n), complex)
+    for k in range(n):
+        e = np.zeros(n, complex)
+        e[k] = 1
+        S[:, k] = oracle.smear(U, e.reshape(-1, 4, 3), dims, alpha, iters).reshape(-1)
+    return S
+
+
+def test_smeared_loops_against_dense(dense_2x2x2x2):
+    dims, U, kappa, M, Minv = dense_2x2x2x2
+    alpha, iters = 0.6, 2
+    S = dense_smearing(U, dims, alpha, iters)
+    assert np.max(np.abs(S - S.conj().T)) < 1e-14
+    gam = [0, 15, 5]
+    got = oracle.loops_z2_smeared(U, dims, kappa, 17, [3], 0, gam, alpha, iters, tol=1e-13)[0]
+    eta = oracle.z2_source(dims, 17, 3).reshape(-1)
+    xi = S @ eta
+    s = Minv @ xi
+    for k, g in enumerate(gam):
+        G = np.kron(np.eye(16), np.kron(oracle.gamma(g), np.eye(3)))
+        per_site = (np.conj(xi) * (G @ s)).reshape(16, 12).sum(axis=1)
+        ref = per_site.reshape(2, 8).sum(axis=1)
+        assert np.max(np.abs(got[k] - ref)) < 1e-11 * np.max(np.abs(ref)), g
+    # the estimator's mean is the trace of the smeared propagator per timeslice
+    B = S @ Minv @ S
+    G5 = np.kron(np.eye(16), np.kron(oracle.gamma(15), np.eye(3)))
+    A = G5 @ B
+    tsl = np.repeat(np.arange(16) // 8, 12)
+    N = 3000
+    est = np.zeros((N, 2), complex)
+    for i in range(N):
+        e = oracle.z2_source(dims, 18, i).reshape(-1)
+        x = S @ e
+        v = np.conj(x) * (G5 @ (Minv @ x))
+        est[i] = [v[tsl == 0].sum(), v[tsl == 1].sum()]
+    exact = [np.trace(A[np.ix_(tsl == t, tsl == t)]) for t in (0, 1)]
+    for t in (0, 1):
+        se = np.std(est[:, t]) / np.sqrt(N)
+        assert abs(est[:, t].mean() - exact[t]) < 4.5 * se, t
 
