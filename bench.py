@@ -185,6 +185,20 @@ def dslash_sweep(dl, torch, G, copy_gbs):
                                    "frac_copy": round(gbs / copy_gbs, 4), "avg_launch_us": round(us, 1),
                                    "launches": n, "config": list(cfg)}
     del G2
+    # one smearing step on 24 right-hand sides (FP64, 12-parameter links), profile kind 4
+    x = torch.zeros((24, G.lattice.V, 4, 3), dtype=torch.complex128, device="cuda")
+    x.real.normal_()
+    dl.smear(G, 0.5, 2, x)
+    torch.cuda.synchronize()
+    dl.dl_profile_enable(True)
+    dl.smear(G, 0.5, 10, x)
+    torch.cuda.synchronize()
+    n, ms, by = dl.dl_profile_read(4)
+    dl.dl_profile_enable(False)
+    del x
+    out["smear_f64_24rhs"] = {"gbs": round(by / (ms * 1e-3) / 1e9, 1), "frac_hbm_peak": round(by / (ms * 1e-3) / 1e9
+                                                                                               / HBM_PEAK_GBS, 4),
+                              "avg_step_us": round(ms / max(n, 1) * 1e3, 1), "steps": n}
     return out
 
 

@@ -285,6 +285,33 @@ int64_t dl_sources_count(dl_lattice lat, const dl_sources *src);
 int dl_sources_fill(dl_lattice lat, const dl_sources *src, int64_t first_rhs, int64_t nrhs, void *out, void *stream);
 
 /*
+ * Gauge-covariant Gaussian smearing of quark fields (Section 2; the paper
+ * uses it for smeared meson operators and gives no parameters):
+ *     S = F^iters,  (F psi)(x) = [ psi(x) + alpha sum_{i=x,y,z} ( U_i(x) psi(x+i)
+ *                                  + U_i(x-i)^+ psi(x-i) ) ] / (1 + 6 alpha),
+ * spin-diagonal, within each timeslice, periodic in space; S is hermitian.
+ * dl_smear: out = S in for device canonical complex128 [nrhs][V][4][3]
+ * fields (in and out must not overlap), computed in FP64 with the FP64 links.
+ * alpha finite and >= 0, iters in [0, 100000] (0 copies), nrhs in
+ * [1, 65535]; the gauge handle must hold FP64 links; else DL_EINVAL.
+ */
+int dl_smear(dl_gauge g, double alpha, int32_t iters, const void *in, void *out, int64_t nrhs, void *stream);
+
+/*
+ * Loops of smeared quark fields: as dl_loops, with the local loop of the
+ * smeared propagator S M^-1 S,
+ *     loops[n][g][t] = sum_d sum_{x: x_4 = t} xi_{n,d}(x)^+ Gamma s(x),
+ *     xi_{n,d} = S eta_{n,d},  M s = xi_{n,d},
+ * (S acts within timeslices and not on spin, and is hermitian, so smearing
+ * the sink is the same as contracting with the smeared noise).  Smearing runs
+ * in FP64; the solve as params says.  Arguments as dl_loops plus alpha and
+ * iters as dl_smear.
+ */
+int dl_loops_smeared(dl_gauge g, double kappa, const dl_sources *sources, double alpha, int32_t iters,
+                     const dl_solve_params *params, const int32_t *gammas, int32_t n_gamma, double *loops,
+                     dl_solve_stats *stats, void *stream);
+
+/*
  * Disconnected two-loop correlator at zero momentum (Section 3, Eq. 2) from
  * per-noise loop estimates of two insertions B and A, e.g. two Gamma slices
  * of the dl_loops output (one lattice, one set of noises):
@@ -314,7 +341,7 @@ int dl_disconnected_correlator(const double *loops_b, const double *loops_a, int
  * links once per launch plus the in/out/epilogue half spinors of each live
  * right-hand side).  kind: 0 = all hopping kernels, 1 = Krylov vector
  * kernels, 2 = sources and traces, 3 = the plain (no epilogue, not adjoint)
- * hopping kernel.  Returns DL_EINVAL for another kind.
+ * hopping kernel, 4 = smearing steps.  Returns DL_EINVAL for another kind.
  */
 int dl_profile_enable(int32_t on);
 int64_t dl_profile_read(int32_t kind, double *ms, double *bytes);

@@ -12,7 +12,7 @@
  * full lattice (no even-odd splitting except where an algorithm's own steps
  * need it), with the 4x4 spin matrices applied as full matrices.
  *
- * Conventions (the paper names "Wilson fermions" and a "basis" but writes
+ * Conventions (the paper names Wilson fermions and refers to a Dirac basis but writes
  * neither down; these are the readings used throughout):
  *   - site index  i = x + X*(y + Y*(z + Z*t)), direction mu = 0,1,2,3 = x,y,z,t;
  *   - spinor  psi[((i*4 + spin)*3 + colour)], complex;

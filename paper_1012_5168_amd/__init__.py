@@ -103,6 +103,10 @@ _SIGNATURES = {
                                 ctypes.POINTER(dl_solve_stats), _P]),
     "dl_loops": (ctypes.c_int, [_P, ctypes.c_double, ctypes.POINTER(dl_sources), ctypes.POINTER(dl_solve_params), _P,
                                 ctypes.c_int32, _P, ctypes.POINTER(dl_solve_stats), _P]),
+    "dl_smear": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int32, _P, _P, ctypes.c_int64, _P]),
+    "dl_loops_smeared": (ctypes.c_int, [_P, ctypes.c_double, ctypes.POINTER(dl_sources), ctypes.c_double,
+                                        ctypes.c_int32, ctypes.POINTER(dl_solve_params), _P, ctypes.c_int32, _P,
+                                        ctypes.POINTER(dl_solve_stats), _P]),
     "dl_loops_tsm": (ctypes.c_int, [_P, ctypes.c_double, ctypes.POINTER(dl_sources), ctypes.POINTER(dl_tsm), _P,
                                     ctypes.c_int32, _P, ctypes.POINTER(dl_solve_stats), _P]),
     "dl_loops_dkappa": (ctypes.c_int, [_P, ctypes.c_double, ctypes.POINTER(dl_sources),
@@ -216,6 +220,20 @@ def dl_loops(gauge, kappa, sources, params, gammas, loops_out: np.ndarray, stats
     g = np.ascontiguousarray(np.asarray(gammas, dtype=np.int32))
     rc = load().dl_loops(gauge, float(kappa), ctypes.byref(sources), ctypes.byref(params), g.ctypes.data_as(_P),
                          len(g), loops_out.ctypes.data_as(_P), stats, _stream(stream))
+    _check(rc, allow=(DL_ENOCONV,))
+    return rc
+
+
+def dl_smear(gauge, alpha, iters, inp, out, nrhs, stream=None):
+    _check(load().dl_smear(gauge, float(alpha), int(iters), _dptr(inp), _dptr(out), int(nrhs), _stream(stream)))
+
+
+def dl_loops_smeared(gauge, kappa, sources, alpha, iters, params, gammas, loops_out: np.ndarray, stats=None,
+                     stream=None):
+    g = np.ascontiguousarray(np.asarray(gammas, dtype=np.int32))
+    rc = load().dl_loops_smeared(gauge, float(kappa), ctypes.byref(sources), float(alpha), int(iters),
+                                 ctypes.byref(params), g.ctypes.data_as(_P), len(g), loops_out.ctypes.data_as(_P),
+                                 stats, _stream(stream))
     _check(rc, allow=(DL_ENOCONV,))
     return rc
 
@@ -376,6 +394,29 @@ def solve(gauge: Gauge, kappa: float, b, params=None):
     x = torch.empty_like(bb)
     _, st = dl_solve(gauge.h, kappa, params, bb, x, bb.shape[0])
     return x.reshape(b.shape), [(s.status, s.iters, s.reliable_updates, s.true_rel_residual) for s in st]
+
+
+def smear(gauge: Gauge, alpha: float, iters: int, psi):
+    """S psi (gauge-covariant Gaussian smearing, FP64) for a device complex128 tensor [n][V][4][3]."""
+    import torch
+
+    x = psi.contiguous()
+    if x.dim() == 3:
+        x = x.unsqueeze(0)
+    out = torch.empty_like(x)
+    dl_smear(gauge.h, alpha, iters, x, out, x.shape[0])
+    return out.reshape(psi.shape)
+
+
+def loops_smeared(gauge: Gauge, kappa: float, sources: dl_sources, alpha: float, iters: int, gammas, params=None,
+                  stream=None):
+    """Per-noise loops of smeared quark fields, complex [n_noise][n_gamma][T], and per-solve stats."""
+    params = params or solve_params()
+    T = gauge.lattice.dims[3]
+    buf = np.zeros((int(sources.n_noise), len(gammas), T, 2), dtype=np.float64)
+    st = (dl_solve_stats * dl_sources_count(gauge.lattice.h, sources))()
+    dl_loops_smeared(gauge.h, kappa, sources, alpha, iters, params, gammas, buf, st, stream)
+    return buf[..., 0] + 1j * buf[..., 1], _stats_list(st)
 
 
 def loops(gauge: Gauge, kappa: float, sources: dl_sources, gammas, params=None, stream=None):

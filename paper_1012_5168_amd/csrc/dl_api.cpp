@@ -1232,9 +1232,12 @@ std::vector<double> adjoint_matrices(const std::vector<double> &gtab, const int3
 //                forward loops) may be null; dout, if set, receives the kappa
 //                derivative as in MODE_DKAPPA (a third solve)
 // stats: per right-hand side and solve ([nsolve][nrhs]) or null.
+// Loop estimates (MODE_LOOPS), their kappa derivative (MODE_DKAPPA) or link
+// gradient (MODE_GRAD).  smear_iters > 0 (MODE_LOOPS only): the sources are
+// smeared, xi = S eta with S = F^smear_iters, and xi serves at the sink too.
 int loops_run(dl_gauge G, double kappa, const dl_sources *src, const dl_solve_params &prm, const int32_t *gammas,
               int n_gamma, int mode, const double *W, double *out_host, double *grad_host, dl_solve_stats *stats,
-              hipStream_t stream, double *dout_host = nullptr)
+              hipStream_t stream, double *dout_host = nullptr, double smear_alpha = 0.0, int smear_iters = 0)
 {
     Ctx c{G, G->lat.geom(), stream};
     const int64_t Vh = G->lat.Vh, V = G->lat.V;
@@ -1244,6 +1247,7 @@ int loops_run(dl_gauge G, double kappa, const dl_sources *src, const dl_solve_pa
     size_t per = (cg ? SolveWork::bytes_cgnr(prm.prec, Vh) : SolveWork::bytes_bicg(prm.prec, Vh)) +
                  (size_t)T * 32 * 8 + 16;
     if (mode == MODE_GRAD) per += 2 * (size_t)Vh * 12 * 16;  // the stored forward solution
+    if (smear_iters > 0) per += 4 * (size_t)Vh * 12 * 16;    // smeared source and its ping-pong partner
     const int64_t total = (int64_t)src->n_noise * ncls;
     const int nsolve = mode == MODE_LOOPS ? 1 : (mode == MODE_GRAD && dout_host) ? 3 : 2;
     const int B = batch_size(per, total, ncls);
@@ -1284,21 +1288,49 @@ int loops_run(dl_gauge G, double kappa, const dl_sources *src, const dl_solve_pa
         ss.point_site = src->point_site;
         ss.noise = dnoise.as<int64_t>();
         ss.cls = dcls.as<int>();
+        // smeared sources: xi = F^iters eta in FP64, kept for the trace
+        HalfField xe, xo, te, to;
+        SourceSpec sx = ss;
+        if (smear_iters > 0) {
+            xe.alloc(P64, n, Vh);
+            xo.alloc(P64, n, Vh);
+            te.alloc(P64, n, Vh);
+            to.alloc(P64, n, Vh);
+            k_source(P64, xe.view(), 0, ss, c.g, n, c.s);
+            k_source(P64, xo.view(), 1, ss, c.g, n, c.s);
+            HalfField *ae = &xe, *ao = &xo, *be = &te, *bo = &to;
+            for (int it = 0; it < smear_iters; ++it) {
+                k_smear(c.links(P64), G->recon, ae->view(), ao->view(), be->view(), bo->view(), c.g, n, smear_alpha,
+                        c.s);
+                std::swap(ae, be);
+                std::swap(ao, bo);
+            }
+            sx.kind = SRC_STORED;
+            sx.xe = ae->view();
+            sx.xo = ao->view();
+        }
+        auto make_source = [&](int prec, Field be, Field bo) {
+            if (smear_iters > 0) {
+                k_copy(prec, be, P64, sx.xe, Vh, n, nullptr, c.s);
+                k_copy(prec, bo, P64, sx.xo, Vh, n, nullptr, c.s);
+            } else {
+                k_source(prec, be, 0, ss, c.g, n, c.s);
+                k_source(prec, bo, 1, ss, c.g, n, c.s);
+            }
+        };
         SolveWork w;
         std::vector<std::vector<dl_solve_stats>> st(nsolve, std::vector<dl_solve_stats>(n));
         int sol_prec = P64;
         if (cg) {
             w.alloc_cgnr(prm.prec, n, Vh);
-            k_source(prm.prec, w.be.view(), 0, ss, c.g, n, c.s);
-            k_source(prm.prec, w.bo.view(), 1, ss, c.g, n, c.s);
+            make_source(prm.prec, w.be.view(), w.bo.view());
             cgnr_batch(c, kappa, prm.fixed_iters, w);
             sol_prec = prm.prec;
             fill_stats(w, {}, st[0].data(), c.s, true);
         } else {
             std::vector<double> res2;
             w.alloc_bicg(prm.prec, n, Vh);
-            k_source(P64, w.be.view(), 0, ss, c.g, n, c.s);
-            k_source(P64, w.bo.view(), 1, ss, c.g, n, c.s);
+            make_source(P64, w.be.view(), w.bo.view());
             bicgstab_batch(c, kappa, prm, w);
             if (stats) true_residual_full(c, kappa, w, res2);
             fill_stats(w, res2, st[0].data(), c.s, false);
@@ -1354,7 +1386,7 @@ int loops_run(dl_gauge G, double kappa, const dl_sources *src, const dl_solve_pa
             }
         }
         if (mode != MODE_GRAD) {
-            k_trace(sol_prec, w.x64.view(), w.xo.view(), ss, c.g, n, dC.as<double>(), c.s);
+            k_trace(sol_prec, w.x64.view(), w.xo.view(), sx, c.g, n, dC.as<double>(), c.s);
             k_gamma_contract(dC.as<double>(), nn, ncls, T, dgam.as<double>(), dgidx.as<int>(), n_gamma,
                              dloops.as<double>() + (r0 / ncls) * n_gamma * T * 2, c.s);
         }
@@ -1393,6 +1425,58 @@ extern "C" int dl_loops(dl_gauge G, double kappa, const dl_sources *src, const d
         check_solver_for(G, *params);
         return loops_run(G, kappa, src, *params, gammas, n_gamma, MODE_LOOPS, nullptr, loops, nullptr, stats,
                          static_cast<hipStream_t>(stream));
+    });
+}
+
+extern "C" int dl_loops_smeared(dl_gauge G, double kappa, const dl_sources *src, double alpha, int32_t iters,
+                                const dl_solve_params *params, const int32_t *gammas, int32_t n_gamma, double *loops,
+                                dl_solve_stats *stats, void *stream)
+{
+    return guarded([&]() {
+        DL_REQUIRE(G && loops, "dl_loops_smeared: null pointer");
+        validate_sources(G->lat, src);
+        validate_params(params);
+        validate_gammas(gammas, n_gamma);
+        check_solver_for(G, *params);
+        DL_REQUIRE(std::isfinite(alpha) && alpha >= 0, "dl_loops_smeared: alpha must be finite and >= 0");
+        DL_REQUIRE(iters >= 0 && iters <= 100000, "dl_loops_smeared: iters must be in [0, 100000]");
+        check_prec(G, P64);
+        return loops_run(G, kappa, src, *params, gammas, n_gamma, MODE_LOOPS, nullptr, loops, nullptr, stats,
+                         static_cast<hipStream_t>(stream), nullptr, alpha, iters);
+    });
+}
+
+extern "C" int dl_smear(dl_gauge G, double alpha, int32_t iters, const void *in, void *out, int64_t nrhs,
+                        void *stream)
+{
+    return guarded([&]() {
+        DL_REQUIRE(G && in && out, "dl_smear: null pointer");
+        DL_REQUIRE(nrhs >= 1 && nrhs <= 65535, "dl_smear: nrhs must be in [1, 65535]");
+        DL_REQUIRE(std::isfinite(alpha) && alpha >= 0, "dl_smear: alpha must be finite and >= 0");
+        DL_REQUIRE(iters >= 0 && iters <= 100000, "dl_smear: iters must be in [0, 100000]");
+        DL_REQUIRE(in != out, "dl_smear: in and out must not overlap");
+        check_prec(G, P64);
+        Ctx c{G, G->lat.geom(), static_cast<hipStream_t>(stream)};
+        const int n = (int)nrhs;
+        const int64_t Vh = G->lat.Vh;
+        HalfField ae, ao, be, bo;
+        ae.alloc(P64, n, Vh);
+        ao.alloc(P64, n, Vh);
+        be.alloc(P64, n, Vh);
+        bo.alloc(P64, n, Vh);
+        k_pack(P64, ae.view(), 0, static_cast<const double *>(in), c.g, n, c.s);
+        k_pack(P64, ao.view(), 1, static_cast<const double *>(in), c.g, n, c.s);
+        HalfField *pe = &ae, *po = &ao, *qe = &be, *qo = &bo;
+        for (int it = 0; it < iters; ++it) {
+            k_smear(c.links(P64), G->recon, pe->view(), po->view(), qe->view(), qo->view(), c.g, n, alpha, c.s);
+            std::swap(pe, qe);
+            std::swap(po, qo);
+        }
+        k_unpack(P64, pe->view(), 0, static_cast<double *>(out), c.g, n, c.s);
+        k_unpack(P64, po->view(), 1, static_cast<double *>(out), c.g, n, c.s);
+        DL_HIP(hipGetLastError());
+        DL_HIP(hipStreamSynchronize(c.s));
+        return DL_OK;
     });
 }
 

@@ -144,7 +144,10 @@ __global__ __launch_bounds__(BS) void trace_kernel(Field se, Field so, SourceSpe
         const int cb = t * per + (j - par * per);
         const Site s = decode(g, cb, par);
         cx<double> eta[12];
-        source_site(src, rhs, s, lex_index(g, s), eta);
+        if (src.kind == SRC_STORED)
+            load_spinor<double>(par ? src.xo : src.xe, g.Vh, rhs, cb, eta);
+        else
+            source_site(src, rhs, s, lex_index(g, s), eta);
         cx<R> sv[12];
         load_spinor<S>(par ? so : se, g.Vh, rhs, cb, sv);
 #pragma unroll
@@ -193,6 +196,56 @@ __global__ void gamma_contract_kernel(const double *C, int ncls, int T, const do
     }
 }
 
+
+// Gauge-covariant Gaussian smearing of quark fields (Section 2), one step on
+// the output parity p:
+//   out(x) = [ in(x) + alpha sum_{i=x,y,z} ( U_i(x) in(x+i) + U_i(x-i)^+ in(x-i) ) ] / (1 + 6 alpha),
+// spin-diagonal (the same colour multiply on all four spins), no boundary
+// sign (space is periodic).  FP64 fields and links.
+template <int NE>
+__global__ __launch_bounds__(BS) void smear_kernel(const void *links, Field in_same, Field in_other, Field out,
+                                                   int parity, Geom g, double alpha, double norm)
+{
+    const int rhs = blockIdx.y;
+    const int cb = blockIdx.x * BS + threadIdx.x;
+    if (cb >= g.Vh) return;
+    const int p = parity, q = 1 - p;
+    const Site s = decode(g, cb, p);
+    int nb[8];
+    neighbours(g, cb, s, nb);
+    cx<double> acc[12];
+#pragma unroll
+    for (int e = 0; e < 12; ++e) acc[e] = {0.0, 0.0};
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        const int mu = d >> 1;
+        const bool fwd = (d & 1) == 0;
+        cx<double> u[9];
+        load_link<double, NE>(links, g.Vh, mu, fwd ? p : q, fwd ? cb : nb[d], u);
+        cx<double> v[12];
+        load_spinor<double>(in_other, g.Vh, rhs, nb[d], v);
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    if (fwd)
+                        cmac(acc[3 * sp + i], u[3 * i + j], v[3 * sp + j]);
+                    else
+                        cmac_conj(acc[3 * sp + i], u[3 * j + i], v[3 * sp + j]);
+                }
+            }
+    }
+    cx<double> x[12];
+    load_spinor<double>(in_same, g.Vh, rhs, cb, x);
+#pragma unroll
+    for (int e = 0; e < 12; ++e) {
+        x[e].re = norm * fma(alpha, acc[e].re, x[e].re);
+        x[e].im = norm * fma(alpha, acc[e].im, x[e].im);
+    }
+    store_spinor<double>(out, g.Vh, rhs, cb, x);
+}
 
 // Disconnected two-loop correlator (Section 3, Eq. 2) from per-noise loops
 // l[n][T] complex (re, im interleaved).  noise_sum_kernel: sum[t] = sum_n l[n][t]
@@ -424,6 +477,23 @@ void k_gamma_contract(const double *C, int n_noise, int ncls, int T, const doubl
                       int n_gamma, double *loops, hipStream_t s)
 {
     hipLaunchKernelGGL(gamma_contract_kernel, dim3(n_noise), dim3(128), 0, s, C, ncls, T, gam, gidx, n_gamma, loops);
+}
+
+void k_smear(const void *links, int recon, Field ine, Field ino, Field oute, Field outo, const Geom &g, int nrhs,
+             double alpha, hipStream_t s)
+{
+    // per step: both parities read once as the centre and once as neighbours' source, written once;
+    // links of the three spatial directions, both parities, once
+    ProfScope ps(PROF_SMEAR, 6 * field_bytes(P64, g.Vh, nrhs) + 2.0 * 3 * g.Vh * (recon == 12 ? 6 : 9) * 16, s);
+    const double norm = 1.0 / (1.0 + 6.0 * alpha);
+    dim3 grid((g.Vh + BS - 1) / BS, nrhs);
+    if (recon == 12) {
+        hipLaunchKernelGGL(smear_kernel<6>, grid, dim3(BS), 0, s, links, ine, ino, oute, 0, g, alpha, norm);
+        hipLaunchKernelGGL(smear_kernel<6>, grid, dim3(BS), 0, s, links, ino, ine, outo, 1, g, alpha, norm);
+    } else {
+        hipLaunchKernelGGL(smear_kernel<9>, grid, dim3(BS), 0, s, links, ine, ino, oute, 0, g, alpha, norm);
+        hipLaunchKernelGGL(smear_kernel<9>, grid, dim3(BS), 0, s, links, ino, ine, outo, 1, g, alpha, norm);
+    }
 }
 
 void k_correlator(const double *lb, const double *la, double *sb, double *sa, int n, int T, double norm, double *out,

@@ -100,7 +100,7 @@ namespace dl {
 
 // ---------------------------------------------------------------- profiling
 
-enum ProfKind { PROF_DSLASH = 0, PROF_BLAS = 1, PROF_TRACE = 2, PROF_DSLASH_PLAIN = 3, PROF_NKIND = 4 };
+enum ProfKind { PROF_DSLASH = 0, PROF_BLAS = 1, PROF_TRACE = 2, PROF_DSLASH_PLAIN = 3, PROF_SMEAR = 4, PROF_NKIND = 5 };
 // Brackets a launch with events when profiling is on.  The algorithmic bytes
 // of the launch are `bytes`, or, when `counter` is set, fixed_bytes (if any
 // work ran) plus unit_bytes times the number of units the kernel counted
@@ -256,8 +256,12 @@ void scalar_launch(int op, const std::vector<SSeg> &segs, const SParams &p, hipS
 void k_pack(int prec, Field dst, int parity, const double *canon, const Geom &g, int nrhs, hipStream_t s);
 void k_unpack(int prec, Field src, int parity, double *canon, const Geom &g, int nrhs, hipStream_t s);
 
+// internal source kind: the source is a stored FP64 field pair (xe, xo), e.g.
+// a smeared noise, instead of being regenerated from the counter stream
+constexpr int SRC_STORED = 100;
+
 struct SourceSpec {
-    int kind;         // DL_SRC_Z2 / DL_SRC_POINT
+    int kind;         // DL_SRC_Z2 / DL_SRC_POINT / SRC_STORED
     int scheme;       // dilution bits
     uint64_t seed;
     int64_t V;
@@ -265,12 +269,18 @@ struct SourceSpec {
     int point_site;
     const int64_t *noise;  // [nrhs] noise number of each right-hand side (device)
     const int *cls;        // [nrhs] dilution class (device); point: 3*spin + colour
+    Field xe = {nullptr, nullptr}, xo = {nullptr, nullptr};  // SRC_STORED: FP64 source per parity
 };
 void k_source(int prec, Field dst, int parity, const SourceSpec &src, const Geom &g, int nrhs, hipStream_t s);
 // C[rhs][t][4][4] (complex) = sum_{x in t} sum_c conj(eta_{a c}(x)) s_{b c}(x)
 void k_trace(int prec, Field se, Field so, const SourceSpec &src, const Geom &g, int nrhs, double *C,
              hipStream_t s);
 // loops[n][g][t] = sum_{d} sum_{ab} Gamma_g[a][b] C[n*ncls + d][t][a][b]
+// one step of gauge-covariant Gaussian smearing on both parities (FP64 fields,
+// FP64 links [4][2][NE][Vh]): out = (in + alpha H in) / (1 + 6 alpha), H the
+// spatial, spin-diagonal hopping term; in and out must not overlap
+void k_smear(const void *links, int recon, Field ine, Field ino, Field oute, Field outo, const Geom &g, int nrhs,
+             double alpha, hipStream_t s);
 // disconnected correlator: out[dt] = -norm * sum over distinct noise pairs (sb, sa: [T] complex scratch)
 void k_correlator(const double *lb, const double *la, double *sb, double *sa, int n, int T, double norm, double *out,
                   hipStream_t s);

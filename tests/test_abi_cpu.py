@@ -77,6 +77,8 @@ def test_null_handles_rejected(dl):
     assert "null" in dl.dl_last_error()
     assert lib.dl_gauge_create(None, None, 1, 12, None, None) == dl.DL_EINVAL
     assert lib.dl_profile_read(7, None, None) == dl.DL_EINVAL
+    assert lib.dl_smear(None, 0.5, 2, None, None, 1, None) == dl.DL_EINVAL
+    assert lib.dl_loops_smeared(None, 0.1, None, 0.5, 2, p, None, 1, None, None, None) == dl.DL_EINVAL
 
 
 def test_correlator_arguments_rejected_before_device_work(dl):
