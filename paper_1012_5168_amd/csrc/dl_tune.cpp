@@ -161,11 +161,18 @@ TuneChoice tune_lookup(const std::vector<DslashCall> &c, hipStream_t s)
         return dflt;
     }
     // repeat until each measurement spans at least ~1 ms of kernel time
+    // The default goes first and a later candidate must beat the best so far
+    // by 3%: near-ties (within timing noise) keep the earlier choice, so the
+    // result does not wander between equivalent configurations.
     TuneChoice best = dflt;
     float best_ms = 1e30f;
     std::vector<DslashCall> t = c;
     for (DslashCall &d : t) d.live_count = nullptr;
-    for (const TuneChoice &cand : candidates(c[0].prec, c[0].recon)) {
+    std::vector<TuneChoice> cands{dflt};
+    for (const TuneChoice &cand : candidates(c[0].prec, c[0].recon))
+        if (!(cand.kind == dflt.kind && cand.nr == dflt.nr && cand.bs == dflt.bs && cand.persistent == dflt.persistent))
+            cands.push_back(cand);
+    for (const TuneChoice &cand : cands) {
         launch_dslash_any(t, cand, s);  // warm
         int reps = 1;
         float ms = 0;
@@ -179,7 +186,7 @@ TuneChoice tune_lookup(const std::vector<DslashCall> &c, hipStream_t s)
             reps *= 8;
         }
         const float per = ms / reps;
-        if (hipGetLastError() == hipSuccess && per < best_ms) {
+        if (hipGetLastError() == hipSuccess && per < 0.97f * best_ms) {
             best_ms = per;
             best = cand;
         }
