@@ -163,3 +163,52 @@ def test_full_size_dkappa_mixed_precision(dl, dev):
     fd = (lp - lm) / (2 * h)
     # FD error ~ h^2 |L'''| + tol |L| / h
     assert rel(fd, d) < 1e-4, rel(fd, d)
+
+
+def test_full_size_tsm_parts(dl, dev):
+    """The truncated-solver workload at full size (16^3 x 32, eps 0.35, kappa 0.150): two LP solves
+    in FP16 storage (25 CGNR iterations) against the oracle's FP64 run of the same iterations, and
+    one HP solve (FP32 with FP64 reliable updates to 1e-10) against the oracle's FP64 solve, through
+    dl_loops_tsm as the benchmark calls it (undiluted noises)."""
+    w = synth.WORKLOADS["tsm_16x16x16x32"]
+    dims, kappa = w["dims"], w["kappa"]
+    U = synth.gauge_field(dims, w["eps"], w["gauge_seed"])
+    G = dl.Gauge(dl.Lattice(dims, 1), U, precs=(dl.DL_F64, dl.DL_F32, dl.DL_F16))
+    gam = [0, 15]
+    lpp = dl.solve_params(solver=dl.DL_CGNR, prec=dl.DL_F16, fixed_iters=25)
+    hpp = dl.solve_params(prec=dl.DL_F32, tol=1e-10, maxiter=1000)
+    a, b, c, st = dl.loops_tsm(G, kappa, dl.z2_sources(w["noise_seed"], 3), 2, 1, gam, lpp, hpp)
+    assert all(s[0] == dl.DL_OK for s in st)
+    ref_lp = oracle.loops_lp(U, dims, kappa, w["noise_seed"], range(3), 0, gam, niter=25)
+    ref_hp = oracle.loops_z2(U, dims, kappa, w["noise_seed"], [2], 0, gam, tol=1e-12)
+    assert rel(a, ref_lp[:2]) < 3e-2, rel(a, ref_lp[:2])
+    assert rel(c, ref_lp[2:]) < 3e-2, rel(c, ref_lp[2:])
+    assert rel(b, ref_hp) < 1e-8, rel(b, ref_hp)
+
+
+def test_full_size_link_gradient_directional(dl, dev):
+    """The differentiation workload's lattice (24^3 x 48, eps 0.35, kappa 0.148), one
+    spin-colour-diluted noise: the link gradient from the adjoint solve against central differences
+    of the loops along a random direction dU (links with three stored rows, FP64 solves)."""
+    w = synth.WORKLOADS["grad_24x24x24x48"]
+    dims, kappa = w["dims"], w["kappa"]
+    U = synth.gauge_field(dims, w["eps"], w["gauge_seed"])
+    lat = dl.Lattice(dims, 1)
+    gam = [15, 0]
+    rng = np.random.default_rng(241)
+    W = rng.standard_normal((1, 2, dims[3])) + 1j * rng.standard_normal((1, 2, dims[3]))
+    prm = dl.solve_params(tol=1e-12, maxiter=2000)
+    src = dl.z2_sources(w["noise_seed"], 1, scheme=dl.DL_DIL_SPIN_COLOUR)
+
+    def F(Ux):
+        L, st = dl.loops(dl.Gauge(lat, Ux, recon=18), kappa, src, gam, prm)
+        assert all(s[0] == dl.DL_OK for s in st)
+        return np.sum((np.conj(W) * L).real)
+
+    grad, _, _, st = dl.loops_link_grad(dl.Gauge(lat, U, recon=18), kappa, src, gam, W, prm)
+    dU = rng.standard_normal(U.shape) + 1j * rng.standard_normal(U.shape)
+    h = 1e-4
+    fd = (F(U + h * dU) - F(U - h * dU)) / (2 * h)
+    an = np.sum((np.conj(grad) * dU).real)
+    # central-difference error ~ h^2 F''' + tol |F| / h; both far below 1e-5 of |an| here
+    assert abs(fd - an) < 1e-5 * abs(an), (fd, an)
