@@ -4,10 +4,14 @@
 //
 // Device layouts (private to the library):
 //   half-spinor field of one parity, one right-hand side: 12 complex
-//   components (spin-major, then colour) stored structure-of-arrays,
-//   component e of checkerboard site cb at [e * Vh + cb]; nrhs fields follow
-//   each other with stride 12 * Vh.  FP16 fields carry an extra FP32 scale
-//   per site ([rhs * Vh + cb]) and store entries divided by it.
+//   components (spin-major, then colour) stored structure-of-arrays in
+//   16-byte vectors of VEC consecutive components (VEC = 1 for FP64, 2 for
+//   FP32, 4 for FP16 / BF16): component e of checkerboard site cb at element
+//   [(e / VEC) * Vh + cb] * VEC + e % VEC, so one lane's 16-byte load brings
+//   VEC components and a wavefront's load covers 64 consecutive sites; nrhs
+//   fields follow each other with stride 12 * Vh elements.  FP16 fields carry
+//   an extra FP32 scale per site ([rhs * Vh + cb]) and store entries divided
+//   by it.
 //   links: [mu][parity][NE][Vh] complex with NE = 6 (rows 0-1, the third row
 //   is rebuilt as the conjugated cross product) or 9.  U_mu(x) of a site x of
 //   parity p sits at [mu][p][.][cb(x)].
@@ -76,25 +80,66 @@ struct Fmt<double> {
     using R = double;
     using E = double2;
     static constexpr bool scaled = false;
+    static constexpr int VEC = 1;
     __device__ static __forceinline__ cx<double> ld(const E *p, int64_t i)
     {
         E v = p[i];
         return {v.x, v.y};
     }
     __device__ static __forceinline__ void st(E *p, int64_t i, cx<double> v) { p[i] = make_double2(v.re, v.im); }
+    // the k-th 16-byte vector of VEC components
+    __device__ static __forceinline__ void ldv(const E *p, int64_t k, cx<double> v[1]) { v[0] = ld(p, k); }
+    __device__ static __forceinline__ void stv(E *p, int64_t k, const cx<double> v[1]) { st(p, k, v[0]); }
 };
 template <>
 struct Fmt<float> {
     using R = float;
     using E = float2;
     static constexpr bool scaled = false;
+    static constexpr int VEC = 2;
     __device__ static __forceinline__ cx<float> ld(const E *p, int64_t i)
     {
         E v = p[i];
         return {v.x, v.y};
     }
     __device__ static __forceinline__ void st(E *p, int64_t i, cx<float> v) { p[i] = make_float2(v.re, v.im); }
+    __device__ static __forceinline__ void ldv(const E *p, int64_t k, cx<float> v[2])
+    {
+        const float4 q = reinterpret_cast<const float4 *>(p)[k];
+        v[0] = {q.x, q.y};
+        v[1] = {q.z, q.w};
+    }
+    __device__ static __forceinline__ void stv(E *p, int64_t k, const cx<float> v[2])
+    {
+        reinterpret_cast<float4 *>(p)[k] = make_float4(v[0].re, v[0].im, v[1].re, v[1].im);
+    }
 };
+
+// four 16-bit complex numbers in one 16-byte vector, as raw 32-bit words
+template <typename H2, typename CVT>
+__device__ __forceinline__ void ldv16(const H2 *p, int64_t k, cx<float> v[4], CVT cvt)
+{
+    const uint4 q = reinterpret_cast<const uint4 *>(p)[k];
+    const unsigned w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        H2 h;
+        __builtin_memcpy(&h, &w[i], 4);
+        const float2 f = cvt(h);
+        v[i] = {f.x, f.y};
+    }
+}
+template <typename H2, typename CVT>
+__device__ __forceinline__ void stv16(H2 *p, int64_t k, const cx<float> v[4], CVT cvt)
+{
+    unsigned w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const H2 h = cvt(make_float2(v[i].re, v[i].im));
+        __builtin_memcpy(&w[i], &h, 4);
+    }
+    reinterpret_cast<uint4 *>(p)[k] = make_uint4(w[0], w[1], w[2], w[3]);
+}
 template <>
 struct Fmt<__half> {
     using R = float;
@@ -108,6 +153,15 @@ struct Fmt<__half> {
     __device__ static __forceinline__ void st(E *p, int64_t i, cx<float> v)
     {
         p[i] = __float22half2_rn(make_float2(v.re, v.im));
+    }
+    static constexpr int VEC = 4;
+    __device__ static __forceinline__ void ldv(const E *p, int64_t k, cx<float> v[4])
+    {
+        ldv16(p, k, v, [](E h) { return __half22float2(h); });
+    }
+    __device__ static __forceinline__ void stv(E *p, int64_t k, const cx<float> v[4])
+    {
+        stv16(p, k, v, [](float2 f) { return __float22half2_rn(f); });
     }
 };
 template <>
@@ -124,6 +178,15 @@ struct Fmt<__hip_bfloat16> {
     {
         p[i] = __float22bfloat162_rn(make_float2(v.re, v.im));
     }
+    static constexpr int VEC = 4;
+    __device__ static __forceinline__ void ldv(const E *p, int64_t k, cx<float> v[4])
+    {
+        ldv16(p, k, v, [](E h) { return __bfloat1622float2(h); });
+    }
+    __device__ static __forceinline__ void stv(E *p, int64_t k, const cx<float> v[4])
+    {
+        stv16(p, k, v, [](float2 f) { return __float22bfloat162_rn(f); });
+    }
 };
 
 // A set of nrhs half-spinor fields of one parity.
@@ -138,9 +201,10 @@ __device__ __forceinline__ void load_spinor(const Field &f, int64_t Vh, int rhs,
 {
     using F = Fmt<S>;
     using R = typename F::R;
-    const typename F::E *p = static_cast<const typename F::E *>(f.d) + (int64_t)rhs * 12 * Vh + cb;
+    constexpr int V = F::VEC;
+    const typename F::E *p = static_cast<const typename F::E *>(f.d) + (int64_t)rhs * 12 * Vh;
 #pragma unroll
-    for (int e = 0; e < 12; ++e) v[e] = F::ld(p, e * Vh);
+    for (int j = 0; j < 12 / V; ++j) F::ldv(p, (int64_t)j * Vh + cb, v + j * V);
     if constexpr (F::scaled) {
         R s = f.nrm[(int64_t)rhs * Vh + cb];
 #pragma unroll
@@ -154,18 +218,22 @@ __device__ __forceinline__ void store_spinor(const Field &f, int64_t Vh, int rhs
 {
     using F = Fmt<S>;
     using R = typename F::R;
-    typename F::E *p = static_cast<typename F::E *>(f.d) + (int64_t)rhs * 12 * Vh + cb;
+    constexpr int V = F::VEC;
+    typename F::E *p = static_cast<typename F::E *>(f.d) + (int64_t)rhs * 12 * Vh;
     if constexpr (F::scaled) {
         R m = 0;
 #pragma unroll
         for (int e = 0; e < 12; ++e) m = fmaxf(m, fmaxf(fabsf(v[e].re), fabsf(v[e].im)));
         f.nrm[(int64_t)rhs * Vh + cb] = m;
         R inv = m > 0 ? R(1) / m : R(0);
+        cx<R> w[12];
 #pragma unroll
-        for (int e = 0; e < 12; ++e) F::st(p, e * Vh, inv * v[e]);
+        for (int e = 0; e < 12; ++e) w[e] = inv * v[e];
+#pragma unroll
+        for (int j = 0; j < 12 / V; ++j) F::stv(p, (int64_t)j * Vh + cb, w + j * V);
     } else {
 #pragma unroll
-        for (int e = 0; e < 12; ++e) F::st(p, e * Vh, v[e]);
+        for (int j = 0; j < 12 / V; ++j) F::stv(p, (int64_t)j * Vh + cb, v + j * V);
     }
 }
 

@@ -227,11 +227,14 @@ __device__ __forceinline__ void dslash_item(const DKArgs &a, int L, double *red)
         any = any || live[r];
     }
     if (!any) return;  // uniform across the block
-    if (a.live_count != nullptr && threadIdx.x == 0) {
+    // profiling: live right-hand-side blocks, counted once per group by its
+    // first site block (the mask is the same for every block of the group;
+    // one atomic per block would contend on the counter)
+    if (a.live_count != nullptr && threadIdx.x == 0 && sb == 0) {
         unsigned nl = 0;
 #pragma unroll
         for (int r = 0; r < NR; ++r) nl += live[r] ? 1u : 0u;
-        atomicAdd(a.live_count, nl);
+        atomicAdd(a.live_count, nl * (unsigned)a.nblk);
     }
 
     const int cb = sb * blockDim.x + threadIdx.x;

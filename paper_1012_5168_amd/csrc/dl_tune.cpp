@@ -17,7 +17,8 @@
 // and regions of 64 blocks where its links fit in LDS, else the item kernel
 // with 1 right-hand side per thread and 256 sites per workgroup;
 // DL_TUNE=item and DL_TUNE=lds pin those two choices (the latter where the
-// LDS-link kernel applies).  The variable is read at every lookup.  Tuning
+// LDS-link kernel applies); DL_TUNE=cfg:kind:nr:bs:grid pins one candidate
+// of the list below (ignored where it is not a candidate).  The variable is read at every lookup.  Tuning
 // never runs while the stream is being captured.
 #include <hip/hip_runtime.h>
 
@@ -65,14 +66,20 @@ std::string cache_path()
     return std::string(home ? home : "/tmp") + "/.cache/dloops/tune_gfx950_v3.txt";
 }
 
-// DL_TUNE: unset or anything else = tune; "0" = default; "item" / "lds" = pinned
-int tune_mode()
+// DL_TUNE: unset or anything else = tune; "0" = default; "item" / "lds" =
+// pinned; "cfg:kind:nr:bs:grid" = that candidate (mode 5, *pin filled in)
+int tune_mode(TuneChoice *pin = nullptr)
 {
     const char *e = std::getenv("DL_TUNE");
     if (!e) return 0;
     if (std::strcmp(e, "0") == 0) return 1;
     if (std::strcmp(e, "item") == 0) return 2;
     if (std::strcmp(e, "lds") == 0) return 3;
+    TuneChoice t;
+    if (pin && std::sscanf(e, "cfg:%d:%d:%d:%d", &t.kind, &t.nr, &t.bs, &t.persistent) == 4) {
+        *pin = t;
+        return 5;
+    }
     return 0;
 }
 
@@ -142,7 +149,9 @@ bool aliases(const std::vector<DslashCall> &cs)
 TuneChoice tune_lookup(const std::vector<DslashCall> &c, hipStream_t s)
 {
     const TuneChoice dflt = default_choice(c[0].prec, c[0].recon);
-    const int mode = tune_mode();
+    TuneChoice pin;
+    const int mode = tune_mode(&pin);
+    if (mode == 5 && valid_choice(pin, c[0].prec, c[0].recon)) return pin;
     if (mode == 2) return TuneChoice{0, 1, 256, 0};
     if (mode == 1 || mode == 3 || aliases(c)) return dflt;
     const Key k = make_key(c);
