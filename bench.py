@@ -45,6 +45,10 @@ def parse():
     ap.add_argument("--dilution-study", action="store_true",
                     help="instead of the timed step: error of the time-averaged loop versus the number of "
                          "inversions for several dilution schemes (Gamma = 1, gamma5, gamma1 gamma3)")
+    ap.add_argument("--batch", action="store_true",
+                    help="instead of the timed step: the batched workload (8^3x16, 12^3x24, 16^3x32, 768 "
+                         "right-hand sides each, FP32 iterations with FP64 reliable updates) with and without "
+                         "graph replay")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the per-precision hopping-kernel sweep and the single-right-hand-side figures")
     return ap.parse_args()
@@ -244,6 +248,49 @@ def dilution_study(dl, G, w, n_noise=16):
             "lattice": list(w["dims"]), "kappa": w["kappa"], "n_noise": n_noise, "schemes": res}
 
 
+def batch_measurement(dl, torch):
+    """The batched workload: three lattices (8^3x16, 12^3x24, 16^3x32; eps 0.30/0.35/0.40; kappa
+    0.145/0.148/0.150), each with 8 complex-Z2 noises x 12 spin-colour x 8 cubic classes = 768
+    right-hand sides, solved together (one launch per kernel over all lattices) in FP32 with FP64
+    reliable updates to 1e-10, L_1 and L_gamma5; timed with hipGraph replay of the iteration chunks
+    and without, after one untimed run that tunes every launch shape."""
+    import synth
+
+    names = ["batch_8x8x8x16", "batch_12x12x12x24", "batch_16x16x16x32"]
+    gs, ks, srcs = [], [], []
+    for nm in names:
+        w = synth.WORKLOADS[nm]
+        U = synth.gauge_field(w["dims"], w["eps"], w["gauge_seed"])
+        gs.append(dl.Gauge(dl.Lattice(w["dims"], 1), U, precs=(dl.DL_F64, dl.DL_F32)))
+        ks.append(w["kappa"])
+        srcs.append(dl.z2_sources(w["noise_seed"], 8, scheme=dl.DL_DIL_SPIN_COLOUR | dl.DL_DIL_CUBIC))
+    out = {"workload": "3 lattices x 768 right-hand sides, FP32 iterations with FP64 reliable updates to 1e-10"}
+    for graph in (True, False):
+        prm = dl.solve_params(prec=dl.DL_F32, tol=1e-10, maxiter=2000, use_graph=graph)
+        dl.batch_loops(gs, ks, srcs, [0, 15], prm)  # tunes
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L, st = dl.batch_loops(gs, ks, srcs, [0, 15], prm)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        nsolve = sum(len(x) for x in st)
+        assert all(s[0] == dl.DL_OK for x in st for s in x)
+        out["graph" if graph else "no_graph"] = {"seconds": round(secs, 3), "solves": nsolve,
+                                                 "solves_per_second": round(nsolve / secs, 1)}
+    # kernel rates from a profiled eager run (launches inside a captured graph carry no events)
+    prm = dl.solve_params(prec=dl.DL_F32, tol=1e-10, maxiter=2000, use_graph=False)
+    dl.dl_profile_enable(True)
+    dl.batch_loops(gs, ks, srcs, [0, 15], prm)
+    torch.cuda.synchronize()
+    n_d, ms_d, by_d = dl.dl_profile_read(0)
+    n_b, ms_b, by_b = dl.dl_profile_read(1)
+    dl.dl_profile_enable(False)
+    out["kernels"] = {"dslash_gbs": round(by_d / (ms_d * 1e-3) / 1e9, 1), "dslash_launches": n_d,
+                      "dslash_ms": round(ms_d, 1), "krylov_vectors_gbs": round(by_b / (ms_b * 1e-3) / 1e9, 1),
+                      "krylov_vectors_ms": round(ms_b, 1)}
+    return out
+
+
 def synth_workload(name):
     import synth
 
@@ -298,6 +345,10 @@ def main():
     stream = torch.cuda.current_stream()
     if args.dilution_study:
         print(json.dumps(dilution_study(dl, G, w)), flush=True)
+        return
+    if args.batch:
+        del G
+        print(json.dumps(batch_measurement(dl, torch)), flush=True)
         return
     prm = dl.solve_params(tol=1e-10, maxiter=1000)
     gam = [0, 15]

@@ -331,6 +331,19 @@ int dl_disconnected_correlator(const double *loops_b, const double *loops_a, int
                                int64_t spatial_volume, double *corr, void *stream);
 
 /*
+ * Device memory cache.  The library keeps the device buffers its calls
+ * release (workspaces, staging) and serves later calls of the same shape from
+ * them instead of allocating again; mapping multi-GB workspaces anew would
+ * otherwise cost seconds per call.  A buffer enters the cache only after the
+ * device has finished its queued work.  The environment variable DL_CACHE_GB
+ * (read once) caps the cached bytes (default 256; 0 disables caching); an
+ * allocation that fails releases the cache and retries once.
+ * dl_cache_release frees every cached buffer (it synchronises the device) and
+ * returns DL_OK.
+ */
+int dl_cache_release(void);
+
+/*
  * Kernel profiling on the library's streams.  dl_profile_enable(1) resets the
  * counters and brackets every following launch with HIP events (and a device
  * counter of the right-hand sides a hopping launch actually processed);

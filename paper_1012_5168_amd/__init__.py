@@ -121,6 +121,7 @@ _SIGNATURES = {
     "dl_sources_fill": (ctypes.c_int, [_P, ctypes.POINTER(dl_sources), ctypes.c_int64, ctypes.c_int64, _P, _P]),
     "dl_disconnected_correlator": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                                   ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "dl_cache_release": (ctypes.c_int, []),
     "dl_profile_enable": (ctypes.c_int, [ctypes.c_int32]),
     "dl_profile_config": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "dl_profile_read": (ctypes.c_int64, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
@@ -312,6 +313,11 @@ def disconnected_correlator(loops_b, loops_a, spatial_volume, stream=None):
     out = np.zeros((T, 2), dtype=np.float64)
     dl_disconnected_correlator(lb, la, n, T, spatial_volume, out, stream)
     return out[:, 0] + 1j * out[:, 1]
+
+
+def dl_cache_release():
+    """Free the device buffers the library keeps for reuse."""
+    _check(load().dl_cache_release())
 
 
 def dl_profile_config(kind: int):

@@ -9,6 +9,7 @@
 #include <complex>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <vector>
@@ -46,24 +47,99 @@ static int guarded(F &&f)
 
 namespace dl {
 
+// Device memory cache.  Workspaces of repeated calls have the same sizes, and
+// mapping a fresh multi-GB allocation costs about as much as the solve it
+// serves, so released buffers are kept per (device, size) and handed out
+// again (a cached block serves a request of at least 4/5 of its size).  A
+// buffer enters the cache only after the device has finished every queued
+// kernel, as hipFree would have waited, so a later call on any stream cannot
+// race with work still reading it.  DL_CACHE_GB caps the cached bytes
+// (default 256; 0 turns the cache off); dl_cache_release frees all of it; an
+// allocation that fails releases the cache and tries again.
+namespace {
+std::mutex g_cache_mu;
+std::multimap<std::pair<int, size_t>, void *> g_cache_free;
+size_t g_cache_bytes = 0;
+
+size_t cache_cap()
+{
+    static const size_t cap = [] {
+        const char *e = std::getenv("DL_CACHE_GB");
+        const double gb = e ? std::atof(e) : 256.0;
+        return gb > 0 ? (size_t)(gb * 1073741824.0) : (size_t)0;
+    }();
+    return cap;
+}
+
+int current_device()
+{
+    int d = 0;
+    (void)hipGetDevice(&d);
+    return d;
+}
+
+void cache_release_all_locked()
+{
+    if (g_cache_free.empty()) return;
+    (void)hipDeviceSynchronize();
+    for (auto &kv : g_cache_free) (void)hipFree(kv.second);
+    g_cache_free.clear();
+    g_cache_bytes = 0;
+}
+}  // namespace
+
 void DevBuf::alloc(size_t n)
 {
     release();
     if (n == 0) return;
+    const int dev = current_device();
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_cache_free.lower_bound({dev, n});
+        if (it != g_cache_free.end() && it->first.first == dev && it->first.second / 5 * 4 <= n) {
+            p = it->second;
+            cap = it->first.second;
+            bytes = n;
+            g_cache_bytes -= cap;
+            g_cache_free.erase(it);
+            return;
+        }
+    }
     hipError_t e = hipMalloc(&p, n);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+        (void)hipGetLastError();
+        {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            cache_release_all_locked();
+        }
+        e = hipMalloc(&p, n);
+    }
     if (e != hipSuccess) {
         p = nullptr;
         (void)hipGetLastError();
         throw Error{DL_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed: " + hipGetErrorString(e)};
     }
-    bytes = n;
+    bytes = cap = n;
 }
 
 void DevBuf::release()
 {
-    if (p) (void)hipFree(p);
+    if (p) {
+        const size_t limit = cache_cap();
+        bool cached = false;
+        if (limit > 0) {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            if (g_cache_bytes + cap <= limit && hipDeviceSynchronize() == hipSuccess) {
+                g_cache_free.insert({{current_device(), cap}, p});
+                g_cache_bytes += cap;
+                cached = true;
+            }
+        }
+        if (!cached) (void)hipFree(p);
+    }
     p = nullptr;
     bytes = 0;
+    cap = 0;
 }
 
 void HalfField::alloc(int prec_, int64_t nrhs_, int64_t Vh_)
@@ -103,7 +179,9 @@ struct ProfRec {
 static std::vector<ProfRec> g_prof_pending;
 static double g_prof_ms[PROF_NKIND], g_prof_bytes[PROF_NKIND];
 static int64_t g_prof_n[PROF_NKIND];
-static DevBuf g_prof_ctr;  // device counters, one per profiled hopping launch and lattice
+// device counters, one per profiled hopping launch and lattice (never destroyed:
+// no HIP call runs during static destruction at process exit)
+static DevBuf &g_prof_ctr = *new DevBuf;
 static TuneChoice g_prof_cfg[PROF_NKIND];  // last profiled hopping configuration per kind
 static bool g_prof_cfg_set[PROF_NKIND];
 static int g_prof_next = 0;
@@ -1684,6 +1762,17 @@ extern "C" int dl_disconnected_correlator(const double *loops_b, const double *l
         DL_HIP(hipGetLastError());
         DL_HIP(hipMemcpyAsync(corr, dout.p, tb, hipMemcpyDeviceToHost, s));
         DL_HIP(hipStreamSynchronize(s));
+        return DL_OK;
+    });
+}
+
+// ====================================================================== memory
+
+extern "C" int dl_cache_release(void)
+{
+    return guarded([&]() {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        cache_release_all_locked();
         return DL_OK;
     });
 }

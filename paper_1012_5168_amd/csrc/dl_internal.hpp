@@ -47,17 +47,18 @@ inline size_t elem_bytes(int p)  // bytes of one stored complex number
 
 struct DevBuf {
     void *p = nullptr;
-    size_t bytes = 0;
+    size_t bytes = 0;  // the requested size: what callers may read or write
+    size_t cap = 0;    // the size of the underlying block (>= bytes when it came from the cache)
     DevBuf() = default;
     explicit DevBuf(size_t n) { alloc(n); }
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), cap(o.cap) { o.p = nullptr; o.bytes = o.cap = 0; }
     DevBuf &operator=(DevBuf &&o) noexcept
     {
         release();
-        p = o.p; bytes = o.bytes;
-        o.p = nullptr; o.bytes = 0;
+        p = o.p; bytes = o.bytes; cap = o.cap;
+        o.p = nullptr; o.bytes = o.cap = 0;
         return *this;
     }
     ~DevBuf() { release(); }
