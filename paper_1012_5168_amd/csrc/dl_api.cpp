@@ -274,7 +274,6 @@ static void prof_drain()
 
 // ====================================================================== dslash launch
 
-int dslash_site_blocks(const Geom &g, int /*prec*/, int /*nrhs*/) { return (g.Vh + 63) / 64; }
 
 template <typename S>
 void launch_dslash_t(const DslashCall *c, int nseg, int kind, int nr, int bs, int persistent, hipStream_t s);

@@ -183,7 +183,6 @@ void launch_dslash_any(const std::vector<DslashCall> &c, const TuneChoice &t, hi
 // links must fit 64 KiB of LDS), and the sites per block a choice gives
 bool dslash_lds_ok(int prec, int recon);
 int dslash_block_sites(const DslashCall &c, const TuneChoice &t);
-int dslash_site_blocks(const Geom &g, int prec, int nrhs);
 
 // ---------------------------------------------------------------- Krylov vector kernels
 
