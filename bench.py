@@ -49,6 +49,9 @@ def parse():
                     help="instead of the timed step: the batched workload (8^3x16, 12^3x24, 16^3x32, 768 "
                          "right-hand sides each, FP32 iterations with FP64 reliable updates) with and without "
                          "graph replay")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="instead of the timed step: only the per-precision hopping-kernel sweep and the "
+                         "single-right-hand-side figures")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the per-precision hopping-kernel sweep and the single-right-hand-side figures")
     return ap.parse_args()
@@ -115,13 +118,26 @@ def tsm_comparison(dl, G, w, L_plain, ms_plain):
     var_p = np.var(L_plain, axis=0, ddof=1) / len(L_plain)
     out = {"ms_tsm": round(ms_tsm, 2), "ms_plain": round(ms_plain, 2), "n_lp": n_lp, "n_hp": n_hp,
            "hp_converged": all(x[0] == dl.DL_OK for x in st[(n_lp + n_hp):])}
+    # bootstrap over noises (LP set, HP set and the plain estimate's noises resampled independently)
+    rng = np.random.default_rng(12345)
+    nboot = 400
+    ratios = np.empty((nboot, len(gam)))
+    for i in range(nboot):
+        il = rng.integers(0, n_lp, n_lp)
+        ih = rng.integers(0, n_hp, n_hp)
+        ip = rng.integers(0, len(L_plain), len(L_plain))
+        _, vtb = dl.tsm_estimate(a[il], b[ih], c[ih])
+        vpb = np.var(L_plain[ip], axis=0, ddof=1) / len(L_plain)
+        ratios[i] = [np.mean(vtb[k].real) / np.mean(vpb[k].real) * ms_tsm / ms_plain for k in range(len(gam))]
     for k, g in enumerate(gam):
         vt = float(np.mean(var_t[k].real))
         vp = float(np.mean(var_p[k].real))
+        lo, hi = np.percentile(ratios[:, k], [16, 84])
         out["gamma%d" % g] = {
             "var_tsm": vt, "var_plain": vp,
             "time_to_equal_variance_ms": round(ms_tsm * vt / vp, 2),
             "ratio_vs_plain": round(ms_tsm * vt / (vp * ms_plain), 4),
+            "ratio_bootstrap_68": [round(float(lo), 4), round(float(hi), 4)],
         }
     return out
 
@@ -350,6 +366,11 @@ def main():
         del G
         print(json.dumps(batch_measurement(dl, torch)), flush=True)
         return
+    if args.sweep_only:
+        cg = copy_rate(torch)  # its copies (2 GiB read, 2 GiB written) also serve as the counters' reference
+        print(json.dumps({"copy_reference_gbs": round(cg, 1), "dslash_by_precision": dslash_sweep(dl, torch, G, cg)}),
+              flush=True)
+        return
     prm = dl.solve_params(tol=1e-10, maxiter=1000)
     gam = [0, 15]
     src = dl.z2_sources(w["noise_seed"], args.noises, scheme=dl.DL_DIL_SPIN_COLOUR)
@@ -439,6 +460,17 @@ def main():
     }
     if not args.no_tsm:
         out["tsm"] = tsm_comparison(dl, G, w, L, ms_step)
+        # the same 288 solves with FP32 iterations and FP64 reliable updates to the same 1e-10
+        pm = dl.solve_params(prec=dl.DL_F32, tol=1e-10, maxiter=2000)
+        dl.loops(G, kappa, src, gam, pm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Lm, stm = dl.loops(G, kappa, src, gam, pm)
+        torch.cuda.synchronize()
+        ms_m = (time.perf_counter() - t0) * 1e3
+        assert all(x[0] == dl.DL_OK for x in stm), "a mixed-precision solve did not converge"
+        out["ms_per_converged_solve_mixed"] = round(ms_m / nrhs, 4)
+        out["mixed_vs_fp64_max_loop_diff_rel"] = float(np.max(np.abs(Lm - L)) / np.max(np.abs(L)))
     if not args.no_sweep:
         cg = copy_rate(torch)
         out["copy_reference_gbs"] = round(cg, 1)
