@@ -318,7 +318,7 @@ def synth_workload(name):
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, KiB -> bytes, mean over the 116
 # dispatches of warm-up + one step), keyed by the launch configuration they
 # were taken with.  Another configuration reports null.
-PROFILED_TRAFFIC = {(1, 2, 64, 64): 13.25e9, (1, 2, 64, 128): 12.09e9}
+PROFILED_TRAFFIC = {}
 
 
 def kernel_name(cfg):
@@ -326,8 +326,9 @@ def kernel_name(cfg):
     kind, nr, bs, pg = cfg
     what = "plain half dslash D_oe, FP64, 12-parameter links"
     if kind == 1:
-        return ("dslash_lds_kernel<double,6,false,0,%d> (%s; links of 64-site blocks in LDS, %d wavefronts, "
-                "regions of %d blocks)" % (nr, what, nr, pg))
+        occ = "as compiled" if bs == 0 else "at most %d per SIMD" % bs
+        return ("dslash_lds_kernel<double,6,false,0,%d,%d> (%s; links of 64-site blocks in LDS, %d wavefronts "
+                "(%s), regions of %d blocks)" % (nr, bs, what, nr, occ, pg))
     return "dslash_kernel<double,6,false,0,%d> (%s; %d sites per workgroup%s)" % (
         nr, what, bs, ", persistent grid of %d" % pg if pg else "")
 

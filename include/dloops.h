@@ -365,10 +365,11 @@ int64_t dl_profile_read(int32_t kind, double *ms, double *bytes);
  * autotuner: cfg[0] = kernel (0 = item kernel, one thread per site and
  * cfg[1] right-hand sides; 1 = LDS-link kernel, links of a 64-site block in
  * LDS and cfg[1] wavefronts walking the right-hand sides), cfg[2] = sites per
- * workgroup, cfg[3] = persistent grid cap (item kernel, 0 = none) or region
- * size in site blocks (LDS-link kernel).  cfg (host, 4 int32) is all -1 when
- * no such launch was profiled since dl_profile_enable(1).  Returns DL_EINVAL
- * for another kind or a null cfg.
+ * workgroup (item kernel) or the wavefronts per SIMD the LDS-link kernel
+ * allows (0 = as compiled), cfg[3] = persistent grid cap (item kernel, 0 =
+ * none) or region size in site blocks (LDS-link kernel).  cfg (host, 4
+ * int32) is all -1 when no such launch was profiled since
+ * dl_profile_enable(1).  Returns DL_EINVAL for another kind or a null cfg.
  */
 int dl_profile_config(int32_t kind, int32_t *cfg);
 

@@ -335,7 +335,6 @@ std::vector<int> launch_dslash_batch(const std::vector<DslashCall> &c0, hipStrea
         std::lock_guard<std::mutex> lk(g_prof_mu);
         TuneChoice used = t;
         if (t.kind == 1 && !dslash_lds_ok(c[0].prec, c[0].recon)) used = TuneChoice{0, 1, 256, 0};
-        if (used.kind == 1) used.bs = 64;
         for (int k : {ps.kind, ps.kind2})
             if (k >= 0 && k < PROF_NKIND) {
                 g_prof_cfg[k] = used;

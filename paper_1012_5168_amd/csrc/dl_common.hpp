@@ -90,6 +90,13 @@ struct Fmt<double> {
     // the k-th 16-byte vector of VEC components
     __device__ static __forceinline__ void ldv(const E *p, int64_t k, cx<double> v[1]) { v[0] = ld(p, k); }
     __device__ static __forceinline__ void stv(E *p, int64_t k, const cx<double> v[1]) { st(p, k, v[0]); }
+    // the components of one 16-byte vector read as raw words
+    __device__ static __forceinline__ void unpack(const uint4 &q, cx<double> v[1])
+    {
+        double2 d;
+        __builtin_memcpy(&d, &q, 16);
+        v[0] = {d.x, d.y};
+    }
 };
 template <>
 struct Fmt<float> {
@@ -113,13 +120,19 @@ struct Fmt<float> {
     {
         reinterpret_cast<float4 *>(p)[k] = make_float4(v[0].re, v[0].im, v[1].re, v[1].im);
     }
+    __device__ static __forceinline__ void unpack(const uint4 &q, cx<float> v[2])
+    {
+        float4 f;
+        __builtin_memcpy(&f, &q, 16);
+        v[0] = {f.x, f.y};
+        v[1] = {f.z, f.w};
+    }
 };
 
 // four 16-bit complex numbers in one 16-byte vector, as raw 32-bit words
 template <typename H2, typename CVT>
-__device__ __forceinline__ void ldv16(const H2 *p, int64_t k, cx<float> v[4], CVT cvt)
+__device__ __forceinline__ void unpack16(const uint4 &q, cx<float> v[4], CVT cvt)
 {
-    const uint4 q = reinterpret_cast<const uint4 *>(p)[k];
     const unsigned w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -128,6 +141,11 @@ __device__ __forceinline__ void ldv16(const H2 *p, int64_t k, cx<float> v[4], CV
         const float2 f = cvt(h);
         v[i] = {f.x, f.y};
     }
+}
+template <typename H2, typename CVT>
+__device__ __forceinline__ void ldv16(const H2 *p, int64_t k, cx<float> v[4], CVT cvt)
+{
+    unpack16<H2>(reinterpret_cast<const uint4 *>(p)[k], v, cvt);
 }
 template <typename H2, typename CVT>
 __device__ __forceinline__ void stv16(H2 *p, int64_t k, const cx<float> v[4], CVT cvt)
@@ -163,6 +181,10 @@ struct Fmt<__half> {
     {
         stv16(p, k, v, [](float2 f) { return __float22half2_rn(f); });
     }
+    __device__ static __forceinline__ void unpack(const uint4 &q, cx<float> v[4])
+    {
+        unpack16<E>(q, v, [](E h) { return __half22float2(h); });
+    }
 };
 template <>
 struct Fmt<__hip_bfloat16> {
@@ -187,6 +209,10 @@ struct Fmt<__hip_bfloat16> {
     {
         stv16(p, k, v, [](float2 f) { return __float22bfloat162_rn(f); });
     }
+    __device__ static __forceinline__ void unpack(const uint4 &q, cx<float> v[4])
+    {
+        unpack16<E>(q, v, [](E h) { return __bfloat1622float2(h); });
+    }
 };
 
 // A set of nrhs half-spinor fields of one parity.
@@ -205,6 +231,43 @@ __device__ __forceinline__ void load_spinor(const Field &f, int64_t Vh, int rhs,
     const typename F::E *p = static_cast<const typename F::E *>(f.d) + (int64_t)rhs * 12 * Vh;
 #pragma unroll
     for (int j = 0; j < 12 / V; ++j) F::ldv(p, (int64_t)j * Vh + cb, v + j * V);
+    if constexpr (F::scaled) {
+        R s = f.nrm[(int64_t)rhs * Vh + cb];
+#pragma unroll
+        for (int e = 0; e < 12; ++e) v[e] = s * v[e];
+    }
+}
+
+// One right-hand side's half-spinor field as a buffer resource (its 12/VEC
+// vectors of 16 bytes per site, vector j of site cb at byte (j Vh + cb) 16).
+// A neighbour's loads then share one per-site byte offset in a VGPR and take
+// the vector offset j Vh 16 from a scalar register: no 64-bit address
+// arithmetic per load.  Requires 12 Vh sizeof(E) < 2^31 (checked by the
+// launcher).  Reads past the resource return zero instead of faulting.
+template <typename S>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t spinor_rsrc(const Field &f, int Vh, int rhs)
+{
+    const int bytes = 12 * Vh * (int)sizeof(typename Fmt<S>::E);
+    char *base = static_cast<char *>(f.d) + (int64_t)rhs * bytes;
+    // word 3: 32-bit data format, the value raw buffer loads use on this family
+    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, bytes, 0x00020000);
+}
+
+template <typename S>
+__device__ __forceinline__ void load_spinor_rsrc(__amdgpu_buffer_rsrc_t rs, const Field &f, int Vh, int rhs, int cb,
+                                                 cx<typename Fmt<S>::R> v[12])
+{
+    using F = Fmt<S>;
+    using R = typename F::R;
+    constexpr int V = F::VEC;
+    const int voff = cb * 16;
+#pragma unroll
+    for (int j = 0; j < 12 / V; ++j) {
+        const auto raw = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, j * Vh * 16, 0);
+        uint4 q;
+        __builtin_memcpy(&q, &raw, 16);
+        F::unpack(q, v + j * V);
+    }
     if constexpr (F::scaled) {
         R s = f.nrm[(int64_t)rhs * Vh + cb];
 #pragma unroll

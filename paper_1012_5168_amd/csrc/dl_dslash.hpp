@@ -145,7 +145,7 @@ constexpr int nparts_c()
 // site's share of the epilogue's reductions in part[].
 template <typename S, int EPI>
 __device__ __forceinline__ void epilogue(const DKArgs &a, int rhs, int64_t cb, const cx<typename Fmt<S>::R> acc[12],
-                                         double part[])
+                                         double part[], bool valid = true)
 {
     using R = typename Fmt<S>::R;
     const R coef = R(a.a);
@@ -167,28 +167,41 @@ __device__ __forceinline__ void epilogue(const DKArgs &a, int rhs, int64_t cb, c
             o[e].re = fma(coef, acc[e].re, xv[e].re);
             o[e].im = fma(coef, acc[e].im, xv[e].im);
         }
+        double p0 = 0.0, p1 = 0.0, p2 = 0.0;
         if constexpr (EPI == EPI_XPAY_DOT) {
             cx<R> yv[12];
             load_spinor<S>(a.y, a.g.Vh, rhs, cb, yv);
 #pragma unroll
             for (int e = 0; e < 12; ++e) {
-                part[0] += (double)yv[e].re * o[e].re + (double)yv[e].im * o[e].im;
-                part[1] += (double)yv[e].re * o[e].im - (double)yv[e].im * o[e].re;
+                p0 += (double)yv[e].re * o[e].re + (double)yv[e].im * o[e].im;
+                p1 += (double)yv[e].re * o[e].im - (double)yv[e].im * o[e].re;
             }
         } else if constexpr (EPI == EPI_XPAY_TS) {
 #pragma unroll
             for (int e = 0; e < 12; ++e) {
-                part[0] += (double)o[e].re * xv[e].re + (double)o[e].im * xv[e].im;
-                part[1] += (double)o[e].re * xv[e].im - (double)o[e].im * xv[e].re;
-                part[2] += (double)o[e].re * o[e].re + (double)o[e].im * o[e].im;
+                p0 += (double)o[e].re * xv[e].re + (double)o[e].im * xv[e].im;
+                p1 += (double)o[e].re * xv[e].im - (double)o[e].im * xv[e].re;
+                p2 += (double)o[e].re * o[e].re + (double)o[e].im * o[e].im;
+            }
+        }
+        if (valid) {
+            if constexpr (EPI == EPI_XPAY_DOT) {
+                part[0] += p0;
+                part[1] += p1;
+            } else if constexpr (EPI == EPI_XPAY_TS) {
+                part[0] += p0;
+                part[1] += p1;
+                part[2] += p2;
             }
         }
     }
     if constexpr (EPI == EPI_XPAY_NRM || EPI == EPI_XMY_NRM) {
+        double p0 = 0.0;
 #pragma unroll
-        for (int e = 0; e < 12; ++e) part[0] += (double)o[e].re * o[e].re + (double)o[e].im * o[e].im;
+        for (int e = 0; e < 12; ++e) p0 += (double)o[e].re * o[e].re + (double)o[e].im * o[e].im;
+        if (valid) part[0] += p0;
     }
-    store_spinor<S>(a.out, a.g.Vh, rhs, cb, o);
+    if (valid) store_spinor<S>(a.out, a.g.Vh, rhs, cb, o);
 }
 
 // neighbour checkerboard indices (x+, x-, y+, y-, z+, z-, t+, t-) of site
@@ -312,7 +325,22 @@ constexpr int lds_link_bytes()
     return 8 * NE * LDS_SITES * (int)sizeof(typename Fmt<S>::E);
 }
 
-template <typename S, int NE, bool DAG, int EPI, int LANES>
+// Reserve registers so that at most OCC wavefronts share a SIMD (0: the
+// occupancy the kernel compiles to).  The register file of a SIMD lane holds
+// 512 registers (VGPRs and AGPRs together): claiming v255 and a31 leaves room
+// for one wavefront, claiming v191 for two.  The FP64 LDS-link kernel runs
+// best at one wavefront per SIMD: fewer right-hand sides in flight per CU keep
+// a region's neighbour spinors in its XCD's L2 (a third less memory traffic).
+template <int OCC>
+__device__ __forceinline__ void reserve_waves()
+{
+    if constexpr (OCC == 1)
+        asm volatile("" ::: "v255", "a31");
+    else if constexpr (OCC == 2)
+        asm volatile("" ::: "v191");
+}
+
+template <typename S, int NE, bool DAG, int EPI, int LANES, int OCC>
 __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArgs> B, int rb)
 {
     using R = typename Fmt<S>::R;
@@ -321,8 +349,11 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
     constexpr int SF = DAG ? +1 : -1;
     constexpr int SB = -SF;
     __shared__ E lk[8 * NE * LDS_SITES];
+    reserve_waves<OCC>();
 
-    const int sl = threadIdx.x & (LDS_SITES - 1), w = threadIdx.x / LDS_SITES;
+    // w is the wavefront's index, uniform across it: said so explicitly, the
+    // per-right-hand-side buffer resources below stay in scalar registers
+    const int sl = threadIdx.x & (LDS_SITES - 1), w = __builtin_amdgcn_readfirstlane(threadIdx.x / LDS_SITES);
     const int total = B.prefix[B.n];
     const int nreg = (total + rb - 1) / rb;
     const int xcd = blockIdx.x % 8, j = blockIdx.x / 8;
@@ -338,24 +369,22 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
         const DKArgs &a = B.a[sg];
         const Geom &g = a.g;
         const int sb = item - B.prefix[sg];
-        const int cb = sb * LDS_SITES + sl;
-        const bool valid = cb < g.Vh;
+        // lanes past the last site mirror it: their loads stay in bounds and
+        // the epilogue stores nothing and adds nothing for them
+        const int cb0 = sb * LDS_SITES + sl;
+        const bool valid = cb0 < g.Vh;
+        const int cb = valid ? cb0 : g.Vh - 1;
         const int p = a.parity, q = 1 - p;
-        Site s = {0, 0, 0, 0};
-        int nb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (valid) {
-            s = decode(g, cb, p);
-            neighbours(g, cb, s, nb);
-        }
+        const Site s = decode(g, cb, p);
+        int nb[8];
+        neighbours(g, cb, s, nb);
         __syncthreads();  // the previous item's links are no longer read
-        if (valid) {
-            for (int d = w; d < 8; d += LANES) {
-                const int mu = d >> 1, bwd = d & 1;
-                const int lcb = bwd ? nb[d] : cb;
-                const E *src = static_cast<const E *>(a.links) + ((int64_t)(mu * 2 + (bwd ? q : p)) * NE) * g.Vh + lcb;
+        for (int d = w; d < 8; d += LANES) {
+            const int mu = d >> 1, bwd = d & 1;
+            const int lcb = bwd ? nb[d] : cb;
+            const E *src = static_cast<const E *>(a.links) + ((int64_t)(mu * 2 + (bwd ? q : p)) * NE) * g.Vh + lcb;
 #pragma unroll
-                for (int e = 0; e < NE; ++e) lk[(d * NE + e) * LDS_SITES + sl] = src[(int64_t)e * g.Vh];
-            }
+            for (int e = 0; e < NE; ++e) lk[(d * NE + e) * LDS_SITES + sl] = src[(int64_t)e * g.Vh];
         }
         __syncthreads();
 
@@ -363,13 +392,22 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
         const R bf = (g.tap && s.t + 1 == g.T) ? R(-1) : R(1);
         const R bb = (g.tap && s.t == 0) ? R(-1) : R(1);
         unsigned nlive = 0;
-        for (int r = w; r < a.nrhs; r += LANES) {  // uniform across the wavefront
-            if (a.active != nullptr && !a.active[r]) continue;
-            ++nlive;
-            double part[NP > 0 ? NP : 1];
+        // Wavefront w takes right-hand sides w, w + LANES, ...  The flags of its
+        // next 64 are read once, one per lane, into a wave-uniform mask, so the
+        // walk itself reads no flag: a flag load inside it would wait for the
+        // previous right-hand side's stores.
+        for (int r0 = w; r0 < a.nrhs; r0 += 64 * LANES) {
+            const int rl = r0 + sl * LANES;
+            const bool on = rl < a.nrhs && (a.active == nullptr || a.active[rl] != 0);
+            uint64_t m = __ballot(on);
+            nlive += (unsigned)__popcll(m);
+            while (m != 0) {
+                const int r = r0 + __builtin_ctzll(m) * LANES;
+                m &= m - 1;
+                const __amdgpu_buffer_rsrc_t rin = spinor_rsrc<S>(a.in, g.Vh, r);
+                double part[NP > 0 ? NP : 1];
 #pragma unroll
-            for (int k = 0; k < (NP > 0 ? NP : 1); ++k) part[k] = 0.0;
-            if (valid) {
+                for (int k = 0; k < (NP > 0 ? NP : 1); ++k) part[k] = 0.0;
                 cx<R> acc[12];
 #pragma unroll
                 for (int e = 0; e < 12; ++e) acc[e] = {R(0), R(0)};
@@ -384,7 +422,7 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
                         u[8] = conj(u[0] * u[4] - u[1] * u[3]);
                     }
                     cx<R> psi[12];
-                    load_spinor<S>(a.in, g.Vh, r, nb[d], psi);
+                    load_spinor_rsrc<S>(rin, a.in, g.Vh, r, nb[d], psi);
                     switch (d) {
                     case 0: hop_mul<R, 0, SF, true>(u, psi, one, acc); break;
                     case 1: hop_mul<R, 0, SB, false>(u, psi, one, acc); break;
@@ -397,15 +435,15 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
                     }
                     pin_acc<R>(acc);
                 }
-                epilogue<S, EPI>(a, r, cb, acc, part);
-            }
-            if constexpr (NP > 0) {
+                epilogue<S, EPI>(a, r, cb, acc, part, valid);
+                if constexpr (NP > 0) {
 #pragma unroll
-                for (int k = 0; k < NP; ++k) part[k] = wave_sum(part[k]);
-                if (sl == 0) {
-                    double *dst = a.partials + ((int64_t)r * a.nblk + sb) * NP;
+                    for (int k = 0; k < NP; ++k) part[k] = wave_sum(part[k]);
+                    if (sl == 0) {
+                        double *dst = a.partials + ((int64_t)r * a.nblk + sb) * NP;
 #pragma unroll
-                    for (int k = 0; k < NP; ++k) dst[k] = part[k];
+                        for (int k = 0; k < NP; ++k) dst[k] = part[k];
+                    }
                 }
             }
         }

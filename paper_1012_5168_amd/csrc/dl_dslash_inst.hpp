@@ -6,17 +6,31 @@
 
 namespace dl {
 
+template <typename S, int NE, bool DAG, int EPI, int LANES>
+static void dslash_go_lds(const Segs<DKArgs> &B, int occ, int grid, int rb, hipStream_t s)
+{
+    if (occ == 1)
+        hipLaunchKernelGGL((dslash_lds_kernel<S, NE, DAG, EPI, LANES, 1>), dim3(grid), dim3(LANES * LDS_SITES), 0, s, B, rb);
+    else if (occ == 2)
+        hipLaunchKernelGGL((dslash_lds_kernel<S, NE, DAG, EPI, LANES, 2>), dim3(grid), dim3(LANES * LDS_SITES), 0, s, B, rb);
+    else
+        hipLaunchKernelGGL((dslash_lds_kernel<S, NE, DAG, EPI, LANES, 0>), dim3(grid), dim3(LANES * LDS_SITES), 0, s, B, rb);
+}
+
+// kind 1 (LDS-link kernel): nr wavefronts per block, `occ` wavefronts per SIMD
+// at most (0: as compiled), regions of rb blocks; kind 0 (item kernel): nr
+// right-hand sides per thread, bs sites per block
 template <typename S, int NE, bool DAG, int EPI>
 static void dslash_go_nr(const Segs<DKArgs> &B, int kind, int nr, int grid, int bs, int rb, hipStream_t s)
 {
     if constexpr (lds_link_bytes<S, NE>() <= 65536) {
         if (kind == 1) {
             if (nr == 4)
-                hipLaunchKernelGGL((dslash_lds_kernel<S, NE, DAG, EPI, 4>), dim3(grid), dim3(4 * LDS_SITES), 0, s, B, rb);
+                dslash_go_lds<S, NE, DAG, EPI, 4>(B, bs, grid, rb, s);
             else if (nr == 2)
-                hipLaunchKernelGGL((dslash_lds_kernel<S, NE, DAG, EPI, 2>), dim3(grid), dim3(2 * LDS_SITES), 0, s, B, rb);
+                dslash_go_lds<S, NE, DAG, EPI, 2>(B, bs, grid, rb, s);
             else
-                hipLaunchKernelGGL((dslash_lds_kernel<S, NE, DAG, EPI, 1>), dim3(grid), dim3(LDS_SITES), 0, s, B, rb);
+                dslash_go_lds<S, NE, DAG, EPI, 1>(B, bs, grid, rb, s);
             return;
         }
     }
@@ -51,17 +65,29 @@ bool dslash_lds_ok_t(int recon)
 // epilogue.  kind 0: the item kernel with nr right-hand sides per thread and
 // bs sites per workgroup; persistent > 0 caps its grid at that many blocks (a
 // multiple of 8).  kind 1: the LDS-link kernel with nr wavefronts per
-// workgroup and regions of `persistent` site blocks.
+// workgroup, at most bs wavefronts per SIMD (0: as compiled) and regions of
+// `persistent` site blocks.
+// whether every segment's per-right-hand-side field fits the 32-bit offsets of
+// the LDS-link kernel's buffer loads
+template <typename S>
+bool dslash_lds_fits(const DslashCall *c, int nseg)
+{
+    for (int k = 0; k < nseg; ++k)
+        if (12LL * c[k].g.Vh * (long long)sizeof(typename Fmt<S>::E) >= (1LL << 31)) return false;
+    return true;
+}
+
 template <typename S>
 void launch_dslash_t(const DslashCall *c, int nseg, int kind, int nr, int bs, int persistent, hipStream_t s)
 {
-    if (kind == 1 && !dslash_lds_ok_t<S>(c[0].recon)) {
+    if (kind == 1 && (!dslash_lds_ok_t<S>(c[0].recon) || !dslash_lds_fits<S>(c, nseg))) {
         kind = 0;
         nr = 1;
         bs = 256;
         persistent = 0;
     }
-    if (kind == 1) bs = LDS_SITES;
+    // the LDS-link kernel's blocks hold LDS_SITES sites; its bs selects the occupancy
+    const int blk = kind == 1 ? LDS_SITES : bs;
     Segs<DKArgs> B;
     B.n = nseg;
     B.prefix[0] = 0;
@@ -76,7 +102,7 @@ void launch_dslash_t(const DslashCall *c, int nseg, int kind, int nr, int bs, in
         a.links = c[k].links;
         a.a = c[k].a;
         a.nrhs = c[k].nrhs;
-        a.nblk = (c[k].g.Vh + bs - 1) / bs;
+        a.nblk = (c[k].g.Vh + blk - 1) / blk;
         a.partials = c[k].partials;
         a.active = c[k].active;
         a.live_count = c[k].live_count;

@@ -5,23 +5,31 @@
 // the workgroup size (64, 128 or 256 sites) and whether the grid is
 // persistent (a capped number of workgroups looping over the work items).
 // The LDS-link kernel's are the wavefronts per workgroup (1, 2 or 4
-// right-hand sides in flight per 64-site block) and the region size (32, 64
-// or 128 site blocks advancing together on one XCD).  The first time a
-// (precision, link format, adjoint,
-// epilogue, right-hand sides, lattices) combination is launched, each
-// candidate is timed
-// with HIP events on the real operands (every hopping launch is idempotent:
-// its output never aliases an input) and the fastest is kept, in memory and
-// in a text cache file (DL_TUNE_CACHE, default ~/.cache/dloops/tune_gfx950_v3.txt).
-// DL_TUNE=0 disables tuning and uses the LDS-link kernel with 2 wavefronts
-// and regions of 64 blocks where its links fit in LDS, else the item kernel
-// with 1 right-hand side per thread and 256 sites per workgroup;
-// DL_TUNE=item and DL_TUNE=lds pin those two choices (the latter where the
-// LDS-link kernel applies); DL_TUNE=cfg:kind:nr:bs:grid pins one candidate
-// of the list below (ignored where it is not a candidate).  The variable is read at every lookup.  Tuning
-// never runs while the stream is being captured.
+// right-hand sides in flight per 64-site block), the wavefronts it allows per
+// SIMD (as compiled, 1 or 2: fewer right-hand sides in flight keep more of a
+// region's neighbour spinors in L2) and the region size (32, 64 or 128 site
+// blocks advancing together on one XCD).  A choice is (kind, nr, bs, grid):
+// kind 0 the item kernel with nr right-hand sides per thread, bs sites per
+// workgroup and a persistent grid of `grid` workgroups (0: one per item);
+// kind 1 the LDS-link kernel with nr wavefronts per workgroup, at most bs
+// wavefronts per SIMD (0: as compiled) and regions of `grid` blocks.  The
+// first time a (precision, link format, adjoint, epilogue, right-hand sides,
+// lattices) combination is launched, each candidate is timed with HIP events
+// on the real operands (every hopping launch is idempotent: its output never
+// aliases an input); a candidate replaces the default only if it is 3%
+// faster, and the result is kept in memory and in a text cache file
+// (DL_TUNE_CACHE, default ~/.cache/dloops/tune_gfx950_v4.txt).
+// DL_TUNE=0 disables tuning and uses the default: the LDS-link kernel with 2
+// wavefronts, one wavefront per SIMD and regions of 64 blocks where its links
+// fit in LDS, else the item kernel with 1 right-hand side per thread and 256
+// sites per workgroup; DL_TUNE=item and DL_TUNE=lds pin those two choices (the
+// latter where the LDS-link kernel applies); DL_TUNE=cfg:kind:nr:bs:grid pins
+// one candidate of the list below (ignored where it is not a candidate).  The
+// variable is read at every lookup.  Tuning never runs while the stream is
+// being captured.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -63,7 +71,7 @@ std::string cache_path()
 {
     if (const char *p = std::getenv("DL_TUNE_CACHE")) return p;
     const char *home = std::getenv("HOME");
-    return std::string(home ? home : "/tmp") + "/.cache/dloops/tune_gfx950_v3.txt";
+    return std::string(home ? home : "/tmp") + "/.cache/dloops/tune_gfx950_v4.txt";
 }
 
 // DL_TUNE: unset or anything else = tune; "0" = default; "item" / "lds" =
@@ -92,7 +100,8 @@ std::vector<TuneChoice> candidates(int prec, int recon)
             for (int pg : {0, PERSIST_GRID}) v.push_back(TuneChoice{0, nr, bs, pg});
     if (dslash_lds_ok(prec, recon))
         for (int lanes : {1, 2, 4})
-            for (int rb : {32, 64, 128}) v.push_back(TuneChoice{1, lanes, 64, rb});
+            for (int occ : {0, 1, 2})
+                for (int rb : {32, 64, 128}) v.push_back(TuneChoice{1, lanes, occ, rb});
     return v;
 }
 
@@ -105,7 +114,7 @@ bool valid_choice(const TuneChoice &t, int prec, int recon)
 
 TuneChoice default_choice(int prec, int recon)
 {
-    return dslash_lds_ok(prec, recon) ? TuneChoice{1, 2, 64, 64} : TuneChoice{0, 1, 256, 0};
+    return dslash_lds_ok(prec, recon) ? TuneChoice{1, 2, 1, 64} : TuneChoice{0, 1, 256, 0};
 }
 
 void load_locked()
@@ -169,10 +178,12 @@ TuneChoice tune_lookup(const std::vector<DslashCall> &c, hipStream_t s)
         (void)hipEventDestroy(e0);
         return dflt;
     }
-    // repeat until each measurement spans at least ~1 ms of kernel time
-    // The default goes first and a later candidate must beat the best so far
-    // by 3%: near-ties (within timing noise) keep the earlier choice, so the
-    // result does not wander between equivalent configurations.
+    // A sample is a run of back-to-back launches spanning at least ~4 ms
+    // (one launch of a 288-right-hand-side hop takes a few ms and varies by a
+    // few percent from launch to launch); a candidate's time is the better of
+    // two samples.  The default goes first and a later candidate must beat
+    // the best so far by 3%: near-ties keep the earlier choice, so the result
+    // does not wander between equivalent configurations.
     TuneChoice best = dflt;
     float best_ms = 1e30f;
     std::vector<DslashCall> t = c;
@@ -181,20 +192,24 @@ TuneChoice tune_lookup(const std::vector<DslashCall> &c, hipStream_t s)
     for (const TuneChoice &cand : candidates(c[0].prec, c[0].recon))
         if (!(cand.kind == dflt.kind && cand.nr == dflt.nr && cand.bs == dflt.bs && cand.persistent == dflt.persistent))
             cands.push_back(cand);
+    auto sample = [&](const TuneChoice &cand, int reps) {
+        float ms = 0;
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps; ++r) launch_dslash_any(t, cand, s);
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        return ms;
+    };
     for (const TuneChoice &cand : cands) {
         launch_dslash_any(t, cand, s);  // warm
         int reps = 1;
-        float ms = 0;
-        for (int attempt = 0; attempt < 3; ++attempt) {
-            (void)hipEventRecord(e0, s);
-            for (int r = 0; r < reps; ++r) launch_dslash_any(t, cand, s);
-            (void)hipEventRecord(e1, s);
-            (void)hipEventSynchronize(e1);
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (ms > 1.0f || reps >= 64) break;
-            reps *= 8;
+        float ms = sample(cand, reps);
+        while (ms < 4.0f && reps < 256) {
+            reps = ms > 0.0f ? std::min(256, std::max(2 * reps, (int)(reps * 4.5f / ms) + 1)) : 2 * reps;
+            ms = sample(cand, reps);
         }
-        const float per = ms / reps;
+        const float per = std::min(ms, sample(cand, reps)) / reps;
         if (hipGetLastError() == hipSuccess && per < 0.97f * best_ms) {
             best_ms = per;
             best = cand;

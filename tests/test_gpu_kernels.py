@@ -1,6 +1,7 @@
-"""Both hopping kernels (the item kernel and the LDS-link kernel) against the
-FP64 oracle, each pinned through DL_TUNE so that neither depends on which one
-the autotuner prefers on the day.
+"""Both hopping kernels (the item kernel and the LDS-link kernel, the latter
+at several wavefront counts, occupancy limits and region sizes) against the
+FP64 oracle, each pinned through DL_TUNE so that none depends on which one the
+autotuner prefers on the day.
 
 Shapes are chosen so that a 64-site block and the region walk have ragged
 ends: 6x4x6x10 has 720 sites per parity (11 full blocks and a 16-site tail),
@@ -31,7 +32,8 @@ def dev():
     return torch.device("cuda:0")
 
 
-@pytest.fixture(params=["item", "lds"])
+# the two default pins, and LDS-link variants with other wavefront counts, occupancy limits and regions
+@pytest.fixture(params=["item", "lds", "cfg:1:2:0:64", "cfg:1:4:2:32", "cfg:1:1:1:128"])
 def kernel(request):
     old = os.environ.get("DL_TUNE")
     os.environ["DL_TUNE"] = request.param
