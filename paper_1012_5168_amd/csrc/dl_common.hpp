@@ -269,7 +269,9 @@ __device__ __forceinline__ void load_spinor_rsrc(__amdgpu_buffer_rsrc_t rs, cons
         F::unpack(q, v + j * V);
     }
     if constexpr (F::scaled) {
-        R s = f.nrm[(int64_t)rhs * Vh + cb];
+        const __amdgpu_buffer_rsrc_t rn =
+            __builtin_amdgcn_make_buffer_rsrc(f.nrm + (int64_t)rhs * Vh, (short)0, Vh * 4, 0x00020000);
+        R s = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rn, cb * 4, 0, 0));
 #pragma unroll
         for (int e = 0; e < 12; ++e) v[e] = s * v[e];
     }

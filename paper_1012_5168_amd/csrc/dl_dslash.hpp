@@ -143,7 +143,18 @@ constexpr int nparts_c()
 // Epilogue for one right-hand side at one site: out = a * acc (PLAIN) or
 // x + a * acc (the XPAY family, with x - y in place of x for XMY), plus this
 // site's share of the epilogue's reductions in part[].
-template <typename S, int EPI>
+// BUF: read x and y through buffer resources (the LDS-link kernel, whose
+// launcher checks that a right-hand side's field fits one).
+template <typename S, bool BUF>
+__device__ __forceinline__ void load_site(const Field &f, int Vh, int rhs, int64_t cb, cx<typename Fmt<S>::R> v[12])
+{
+    if constexpr (BUF)
+        load_spinor_rsrc<S>(spinor_rsrc<S>(f, Vh, rhs), f, Vh, rhs, (int)cb, v);
+    else
+        load_spinor<S>(f, Vh, rhs, cb, v);
+}
+
+template <typename S, int EPI, bool BUF = false>
 __device__ __forceinline__ void epilogue(const DKArgs &a, int rhs, int64_t cb, const cx<typename Fmt<S>::R> acc[12],
                                          double part[], bool valid = true)
 {
@@ -155,10 +166,10 @@ __device__ __forceinline__ void epilogue(const DKArgs &a, int rhs, int64_t cb, c
         for (int e = 0; e < 12; ++e) o[e] = coef * acc[e];
     } else {
         cx<R> xv[12];
-        load_spinor<S>(a.x, a.g.Vh, rhs, cb, xv);
+        load_site<S, BUF>(a.x, a.g.Vh, rhs, cb, xv);
         if constexpr (EPI == EPI_XMY_NRM) {
             cx<R> yv[12];
-            load_spinor<S>(a.y, a.g.Vh, rhs, cb, yv);
+            load_site<S, BUF>(a.y, a.g.Vh, rhs, cb, yv);
 #pragma unroll
             for (int e = 0; e < 12; ++e) xv[e] = xv[e] - yv[e];
         }
@@ -170,7 +181,7 @@ __device__ __forceinline__ void epilogue(const DKArgs &a, int rhs, int64_t cb, c
         double p0 = 0.0, p1 = 0.0, p2 = 0.0;
         if constexpr (EPI == EPI_XPAY_DOT) {
             cx<R> yv[12];
-            load_spinor<S>(a.y, a.g.Vh, rhs, cb, yv);
+            load_site<S, BUF>(a.y, a.g.Vh, rhs, cb, yv);
 #pragma unroll
             for (int e = 0; e < 12; ++e) {
                 p0 += (double)yv[e].re * o[e].re + (double)yv[e].im * o[e].im;
@@ -435,7 +446,7 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
                     }
                     pin_acc<R>(acc);
                 }
-                epilogue<S, EPI>(a, r, cb, acc, part, valid);
+                epilogue<S, EPI, true>(a, r, cb, acc, part, valid);
                 if constexpr (NP > 0) {
 #pragma unroll
                     for (int k = 0; k < NP; ++k) part[k] = wave_sum(part[k]);
