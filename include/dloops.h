@@ -331,6 +331,29 @@ int dl_disconnected_correlator(const double *loops_b, const double *loops_a, int
                                int64_t spatial_volume, double *corr, void *stream);
 
 /*
+ * The flavour-singlet pseudoscalar combination and the ratio fit of Section 3
+ * (Eqs. 3 and 4), on correlators the caller has averaged per gauge
+ * configuration: d[n][t] the disconnected correlator D(t) (e.g. the real part
+ * of dl_disconnected_correlator), c_pi[n][t] the connected pion correlator
+ * C_pi(t), n = 0 .. ncfg-1, t = 0 .. T-1 (host, row-major FP64).
+ *     c_eta[t] = mean_n (C_pi - 2 D)(t)                            (Eq. 3)
+ *     R(t) = sum_n D / sum_n C_pi  fitted on tmin <= t <= tmax to
+ *     A - B (e^{-m t} + e^{-m (T - t)}) / (e^{-m_pi t} + e^{-m_pi (T - t)})   (Eq. 4)
+ * with m_pi given (the prior): params[3] = (A, B, m) where m is the
+ * eta' mass, the one minimising chi^2 = sum_t w_t (R - model)^2 over m in
+ * [1e-3, 10] (lattice units); w_t = 1 / var R(t) from a jackknife over
+ * configurations when ncfg >= 2 (unit weights otherwise, or where a variance
+ * vanishes).  errors[3]: jackknife errors of (A, B, m) (each sample refitted
+ * with the same weights; zeros when ncfg < 2).  *chi2: the fit's chi^2.
+ * Host computation, no device work.  Returns DL_EINVAL for a null pointer,
+ * ncfg < 1, T outside [4, 65535], fewer than 4 points in [tmin, tmax] (or
+ * the range outside [0, T)), m_pi <= 0, or a zero / non-finite configuration
+ * sum of C_pi in the fit range.
+ */
+int dl_eta_prime_fit(const double *d, const double *c_pi, int32_t ncfg, int32_t T, double m_pi, int32_t tmin,
+                     int32_t tmax, double *c_eta, double *params, double *errors, double *chi2);
+
+/*
  * Device memory cache.  The library keeps the device buffers its calls
  * release (workspaces, staging) and serves later calls of the same shape from
  * them instead of allocating again; mapping multi-GB workspaces anew would

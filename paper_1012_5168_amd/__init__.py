@@ -121,6 +121,8 @@ _SIGNATURES = {
     "dl_sources_fill": (ctypes.c_int, [_P, ctypes.POINTER(dl_sources), ctypes.c_int64, ctypes.c_int64, _P, _P]),
     "dl_disconnected_correlator": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                                   ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "dl_eta_prime_fit": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                        ctypes.c_int32, _P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
     "dl_cache_release": (ctypes.c_int, []),
     "dl_profile_enable": (ctypes.c_int, [ctypes.c_int32]),
     "dl_profile_config": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
@@ -313,6 +315,28 @@ def disconnected_correlator(loops_b, loops_a, spatial_volume, stream=None):
     out = np.zeros((T, 2), dtype=np.float64)
     dl_disconnected_correlator(lb, la, n, T, spatial_volume, out, stream)
     return out[:, 0] + 1j * out[:, 1]
+
+
+def dl_eta_prime_fit(d, c_pi, ncfg, T, m_pi, tmin, tmax, c_eta, params, errors):
+    chi2 = ctypes.c_double()
+    _check(load().dl_eta_prime_fit(d.ctypes.data, c_pi.ctypes.data, int(ncfg), int(T), float(m_pi), int(tmin),
+                                   int(tmax), c_eta.ctypes.data, params.ctypes.data, errors.ctypes.data,
+                                   ctypes.byref(chi2)))
+    return chi2.value
+
+
+def eta_prime_fit(d, c_pi, m_pi, tmin, tmax):
+    """Eqs. 3-4 on per-configuration correlators d, c_pi (real [ncfg][T] or [T]): returns
+    (c_eta[T], (A, B, m_eta'), jackknife errors, chi2)."""
+    d = np.ascontiguousarray(np.atleast_2d(np.asarray(d, dtype=np.float64)))
+    c = np.ascontiguousarray(np.atleast_2d(np.asarray(c_pi, dtype=np.float64)))
+    if d.shape != c.shape:
+        raise ValueError("d and c_pi must have the same shape")
+    ncfg, T = d.shape
+    c_eta = np.zeros(T)
+    params, errors = np.zeros(3), np.zeros(3)
+    chi2 = dl_eta_prime_fit(d, c, ncfg, T, m_pi, tmin, tmax, c_eta, params, errors)
+    return c_eta, params, errors, chi2
 
 
 def dl_cache_release():

@@ -1764,6 +1764,16 @@ extern "C" int dl_disconnected_correlator(const double *loops_b, const double *l
     });
 }
 
+extern "C" int dl_eta_prime_fit(const double *d, const double *c_pi, int32_t ncfg, int32_t T, double m_pi,
+                                int32_t tmin, int32_t tmax, double *c_eta, double *params, double *errors,
+                                double *chi2)
+{
+    return guarded([&]() {
+        eta_prime_fit(d, c_pi, ncfg, T, m_pi, tmin, tmax, c_eta, params, errors, chi2);
+        return DL_OK;
+    });
+}
+
 // ====================================================================== memory
 
 extern "C" int dl_cache_release(void)

@@ -282,6 +282,9 @@ void k_trace(int prec, Field se, Field so, const SourceSpec &src, const Geom &g,
 void k_smear(const void *links, int recon, Field ine, Field ino, Field oute, Field outo, const Geom &g, int nrhs,
              double alpha, hipStream_t s);
 // disconnected correlator: out[dt] = -norm * sum over distinct noise pairs (sb, sa: [T] complex scratch)
+// Eqs. 3-4 (dl_fit.cpp): the flavour-singlet combination and the ratio fit
+void eta_prime_fit(const double *d, const double *c, int ncfg, int T, double m_pi, int tmin, int tmax, double *c_eta,
+                   double *params, double *errors, double *chi2);
 void k_correlator(const double *lb, const double *la, double *sb, double *sa, int n, int T, double norm, double *out,
                   hipStream_t s);
 void k_gamma_contract(const double *C, int n_noise, int ncls, int T, const double *gam, const int *gidx,

@@ -97,6 +97,34 @@ def test_correlator_arguments_rejected_before_device_work(dl):
     assert lib.dl_disconnected_correlator(p, p, 3, 4, 8, None, None) == dl.DL_EINVAL
 
 
+def test_eta_prime_fit_arguments_rejected(dl):
+    """Null pointers, too few fit points, a range outside [0, T), a non-positive pion mass or a zero
+    connected correlator in the range return DL_EINVAL (host-only entry: no device work in any case)."""
+    import ctypes
+
+    import numpy as np
+
+    lib = dl.load()
+    T = 16
+    d = np.zeros((2, T))
+    c = np.ones((2, T))
+    ce, pa, er = np.zeros(T), np.zeros(3), np.zeros(3)
+    chi = ctypes.c_double()
+    D, C, E, P, R = d.ctypes.data, c.ctypes.data, ce.ctypes.data, pa.ctypes.data, er.ctypes.data
+
+    def call(dp, cp, n, t, mpi, a, b):
+        return lib.dl_eta_prime_fit(dp, cp, n, t, mpi, a, b, E, P, R, ctypes.byref(chi))
+
+    assert call(None, C, 2, T, 0.5, 1, 8) == dl.DL_EINVAL
+    assert call(D, C, 0, T, 0.5, 1, 8) == dl.DL_EINVAL
+    assert call(D, C, 2, 3, 0.5, 0, 2) == dl.DL_EINVAL
+    assert call(D, C, 2, T, 0.5, 5, 7) == dl.DL_EINVAL
+    assert call(D, C, 2, T, 0.5, 1, T) == dl.DL_EINVAL
+    assert call(D, C, 2, T, 0.0, 1, 8) == dl.DL_EINVAL
+    c[:, 4] = 0.0
+    assert call(D, C, 2, T, 0.5, 1, 8) == dl.DL_EINVAL
+
+
 def test_product_never_reaches_the_oracle():
     pkg = os.path.join(ROOT, "paper_1012_5168_amd")
     for dirpath, _, files in os.walk(pkg):

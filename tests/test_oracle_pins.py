@@ -39,6 +39,13 @@ that does not share its code:
   unbiasedness over distinct noise pairs when the two loops of one noise are
   correlated (z-test), with the same-noise estimator shown to be biased on the
   same data; the B <-> A swap symmetry D^BA(dt) = D^AB(T - dt).
+* eta' combination and ratio fit (Eqs. 3-4): noise-free correlators built
+  here from chosen (A, B, m_eta', m_pi) are fitted back exactly, and a wrong
+  sign of B or a dropped backward-propagating term in the model would not
+  fit them; Eq. 3 elementwise; configurations that differ only by a factor
+  have zero jackknife errors; configurations whose ratios differ only in A
+  give A's jackknife error as the standard error of the mean of the A_n
+  (the closed form of the jackknife for a mean) and zero errors for B and m.
 """
 import itertools
 
@@ -766,3 +773,60 @@ def test_smeared_loops_against_dense(dense_2x2x2x2):
         se = np.std(est[:, t]) / np.sqrt(N)
         assert abs(est[:, t].mean() - exact[t]) < 4.5 * se, t
 
+
+
+# ------------------------------------------------------------ eta' ratio fit (Eqs. 3-4)
+
+
+def _ratio_model(T, m_pi, A, B, m):
+    t = np.arange(T)
+    gp = np.exp(-m_pi * t) + np.exp(-m_pi * (T - t))
+    gm = np.exp(-m * t) + np.exp(-m * (T - t))
+    return gp, A - B * gm / gp
+
+
+def test_eta_prime_fit_recovers_noise_free_parameters():
+    T, m_pi = 32, 0.6
+    for A, B, m in [(0.8, 0.5, 0.45), (-0.2, 1.3, 0.9), (0.05, 0.02, 0.3)]:
+        gp, r = _ratio_model(T, m_pi, A, B, m)
+        C = 2.5 * gp
+        D = C * r
+        c_eta, p, err, chi2 = oracle.eta_prime_fit(D, C, m_pi, 2, 11)
+        assert np.allclose(p, [A, B, m], rtol=1e-8, atol=1e-10), (p, A, B, m)
+        assert chi2 < 1e-20 and np.all(err == 0)
+        assert np.allclose(c_eta, C - 2 * D, rtol=1e-15, atol=0)
+        # a model with the other sign of B, or without the backward term e^{-m (T-t)}, cannot fit these data
+        t = np.arange(2, 12)
+        wrong = [A + B * (np.exp(-m * t) + np.exp(-m * (T - t))) / gp[2:12],
+                 A - B * np.exp(-m * t) / gp[2:12]]
+        for wr in wrong:
+            assert np.max(np.abs(wr - r[2:12])) > 1e-6
+
+
+def test_eta_prime_fit_scaled_configurations_have_no_spread():
+    T, m_pi = 24, 0.7
+    gp, r = _ratio_model(T, m_pi, 0.6, 0.4, 0.5)
+    lam = np.array([0.7, 1.0, 1.3, 2.1])[:, None]
+    C = lam * gp[None]
+    D = C * r[None]
+    c_eta, p, err, chi2 = oracle.eta_prime_fit(D, C, m_pi, 1, 10)
+    assert np.allclose(p, [0.6, 0.4, 0.5], rtol=1e-8)
+    assert np.all(np.abs(err) < 1e-9)
+    assert np.allclose(c_eta, (C - 2 * D).mean(axis=0), rtol=1e-14)
+
+
+def test_eta_prime_fit_jackknife_of_a_shift_in_A():
+    """Per-configuration ratios A_n - B g: every jackknife sample has the same B and m, and A_k is the
+    leave-one-out mean, so the jackknife error of A is the standard error of the mean of the A_n."""
+    T, m_pi, B, m = 32, 0.6, 0.5, 0.45
+    rng = np.random.default_rng(71)
+    An = 0.8 + 0.05 * rng.standard_normal(9)
+    gp, _ = _ratio_model(T, m_pi, 0.0, B, m)
+    t = np.arange(T)
+    g = (np.exp(-m * t) + np.exp(-m * (T - t))) / gp
+    C = np.tile(3.0 * gp, (len(An), 1))
+    D = C * (An[:, None] - B * g[None])
+    _, p, err, _ = oracle.eta_prime_fit(D, C, m_pi, 2, 12)
+    sem = np.sqrt(np.sum((An - An.mean()) ** 2) / (len(An) * (len(An) - 1)))
+    assert np.allclose(p, [An.mean(), B, m], rtol=1e-7)
+    assert abs(err[0] - sem) < 1e-7 * sem and err[1] < 1e-8 and err[2] < 1e-8, (err, sem)
