@@ -97,6 +97,13 @@ struct Fmt<double> {
         __builtin_memcpy(&d, &q, 16);
         v[0] = {d.x, d.y};
     }
+    __device__ static __forceinline__ uint4 pack(const cx<double> v[1])
+    {
+        const double2 d = make_double2(v[0].re, v[0].im);
+        uint4 q;
+        __builtin_memcpy(&q, &d, 16);
+        return q;
+    }
 };
 template <>
 struct Fmt<float> {
@@ -127,6 +134,13 @@ struct Fmt<float> {
         v[0] = {f.x, f.y};
         v[1] = {f.z, f.w};
     }
+    __device__ static __forceinline__ uint4 pack(const cx<float> v[2])
+    {
+        const float4 f = make_float4(v[0].re, v[0].im, v[1].re, v[1].im);
+        uint4 q;
+        __builtin_memcpy(&q, &f, 16);
+        return q;
+    }
 };
 
 // four 16-bit complex numbers in one 16-byte vector, as raw 32-bit words
@@ -148,7 +162,7 @@ __device__ __forceinline__ void ldv16(const H2 *p, int64_t k, cx<float> v[4], CV
     unpack16<H2>(reinterpret_cast<const uint4 *>(p)[k], v, cvt);
 }
 template <typename H2, typename CVT>
-__device__ __forceinline__ void stv16(H2 *p, int64_t k, const cx<float> v[4], CVT cvt)
+__device__ __forceinline__ uint4 pack16(const cx<float> v[4], CVT cvt)
 {
     unsigned w[4];
 #pragma unroll
@@ -156,7 +170,12 @@ __device__ __forceinline__ void stv16(H2 *p, int64_t k, const cx<float> v[4], CV
         const H2 h = cvt(make_float2(v[i].re, v[i].im));
         __builtin_memcpy(&w[i], &h, 4);
     }
-    reinterpret_cast<uint4 *>(p)[k] = make_uint4(w[0], w[1], w[2], w[3]);
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+template <typename H2, typename CVT>
+__device__ __forceinline__ void stv16(H2 *p, int64_t k, const cx<float> v[4], CVT cvt)
+{
+    reinterpret_cast<uint4 *>(p)[k] = pack16<H2>(v, cvt);
 }
 template <>
 struct Fmt<__half> {
@@ -185,6 +204,10 @@ struct Fmt<__half> {
     {
         unpack16<E>(q, v, [](E h) { return __half22float2(h); });
     }
+    __device__ static __forceinline__ uint4 pack(const cx<float> v[4])
+    {
+        return pack16<E>(v, [](float2 f) { return __float22half2_rn(f); });
+    }
 };
 template <>
 struct Fmt<__hip_bfloat16> {
@@ -212,6 +235,10 @@ struct Fmt<__hip_bfloat16> {
     __device__ static __forceinline__ void unpack(const uint4 &q, cx<float> v[4])
     {
         unpack16<E>(q, v, [](E h) { return __bfloat1622float2(h); });
+    }
+    __device__ static __forceinline__ uint4 pack(const cx<float> v[4])
+    {
+        return pack16<E>(v, [](float2 f) { return __float22bfloat162_rn(f); });
     }
 };
 
@@ -253,7 +280,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t spinor_rsrc(const Field &f, in
     return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, bytes, 0x00020000);
 }
 
-template <typename S>
+// AUX: the loads' cache policy (0 = default; 2 = non-temporal, for data read
+// once, so that it does not displace reused lines in L2).
+template <typename S, int AUX = 0>
 __device__ __forceinline__ void load_spinor_rsrc(__amdgpu_buffer_rsrc_t rs, const Field &f, int Vh, int rhs, int cb,
                                                  cx<typename Fmt<S>::R> v[12])
 {
@@ -263,7 +292,7 @@ __device__ __forceinline__ void load_spinor_rsrc(__amdgpu_buffer_rsrc_t rs, cons
     const int voff = cb * 16;
 #pragma unroll
     for (int j = 0; j < 12 / V; ++j) {
-        const auto raw = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, j * Vh * 16, 0);
+        const auto raw = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, j * Vh * 16, AUX);
         uint4 q;
         __builtin_memcpy(&q, &raw, 16);
         F::unpack(q, v + j * V);
@@ -277,28 +306,44 @@ __device__ __forceinline__ void load_spinor_rsrc(__amdgpu_buffer_rsrc_t rs, cons
     }
 }
 
-template <typename S>
+// NT: non-temporal stores (written once, not read again by this launch: they
+// need not displace the lines the launch reuses in L2)
+template <typename S, bool NT = false>
 __device__ __forceinline__ void store_spinor(const Field &f, int64_t Vh, int rhs, int64_t cb,
                                              const cx<typename Fmt<S>::R> v[12])
 {
     using F = Fmt<S>;
     using R = typename F::R;
+    using U4 = unsigned __attribute__((ext_vector_type(4)));
     constexpr int V = F::VEC;
     typename F::E *p = static_cast<typename F::E *>(f.d) + (int64_t)rhs * 12 * Vh;
+    auto put = [&](int64_t k, const cx<R> *w) {
+        if constexpr (NT) {
+            const uint4 q = F::pack(w);
+            U4 raw;
+            __builtin_memcpy(&raw, &q, 16);
+            __builtin_nontemporal_store(raw, reinterpret_cast<U4 *>(p) + k);
+        } else {
+            F::stv(p, k, w);
+        }
+    };
     if constexpr (F::scaled) {
         R m = 0;
 #pragma unroll
         for (int e = 0; e < 12; ++e) m = fmaxf(m, fmaxf(fabsf(v[e].re), fabsf(v[e].im)));
-        f.nrm[(int64_t)rhs * Vh + cb] = m;
+        if constexpr (NT)
+            __builtin_nontemporal_store(m, f.nrm + (int64_t)rhs * Vh + cb);
+        else
+            f.nrm[(int64_t)rhs * Vh + cb] = m;
         R inv = m > 0 ? R(1) / m : R(0);
         cx<R> w[12];
 #pragma unroll
         for (int e = 0; e < 12; ++e) w[e] = inv * v[e];
 #pragma unroll
-        for (int j = 0; j < 12 / V; ++j) F::stv(p, (int64_t)j * Vh + cb, w + j * V);
+        for (int j = 0; j < 12 / V; ++j) put((int64_t)j * Vh + cb, w + j * V);
     } else {
 #pragma unroll
-        for (int j = 0; j < 12 / V; ++j) F::stv(p, (int64_t)j * Vh + cb, v + j * V);
+        for (int j = 0; j < 12 / V; ++j) put((int64_t)j * Vh + cb, v + j * V);
     }
 }
 

@@ -149,7 +149,7 @@ template <typename S, bool BUF>
 __device__ __forceinline__ void load_site(const Field &f, int Vh, int rhs, int64_t cb, cx<typename Fmt<S>::R> v[12])
 {
     if constexpr (BUF)
-        load_spinor_rsrc<S>(spinor_rsrc<S>(f, Vh, rhs), f, Vh, rhs, (int)cb, v);
+        load_spinor_rsrc<S, 2>(spinor_rsrc<S>(f, Vh, rhs), f, Vh, rhs, (int)cb, v);
     else
         load_spinor<S>(f, Vh, rhs, cb, v);
 }
@@ -212,7 +212,7 @@ __device__ __forceinline__ void epilogue(const DKArgs &a, int rhs, int64_t cb, c
         for (int e = 0; e < 12; ++e) p0 += (double)o[e].re * o[e].re + (double)o[e].im * o[e].im;
         if (valid) part[0] += p0;
     }
-    if (valid) store_spinor<S>(a.out, a.g.Vh, rhs, cb, o);
+    if (valid) store_spinor<S, BUF>(a.out, a.g.Vh, rhs, cb, o);
 }
 
 // neighbour checkerboard indices (x+, x-, y+, y-, z+, z-, t+, t-) of site
