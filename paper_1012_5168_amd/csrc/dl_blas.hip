@@ -276,7 +276,7 @@ __device__ __forceinline__ void vec_item(const VSeg &a, int item, double *red)
         load_spinor<S>(a.f[2], Vh, rhs, cb, vv);
 #pragma unroll
         for (int e = 0; e < 12; ++e) pv[e] = rv[e] + beta * (pv[e] - omega * vv[e]);
-        store_spinor<S>(a.f[0], Vh, rhs, cb, pv);
+        store_spinor<S, true>(a.f[0], Vh, rhs, cb, pv);
     } else if constexpr (OP == V_BICG_S) {
         if (!valid) return;
         const cx<R> alpha = ld_c<R>(a.st[rhs].alpha);
@@ -285,7 +285,7 @@ __device__ __forceinline__ void vec_item(const VSeg &a, int item, double *red)
         load_spinor<S>(a.f[1], Vh, rhs, cb, vv);
 #pragma unroll
         for (int e = 0; e < 12; ++e) rv[e] = rv[e] - alpha * vv[e];
-        store_spinor<S>(a.f[0], Vh, rhs, cb, rv);
+        store_spinor<S, true>(a.f[0], Vh, rhs, cb, rv);
     } else if constexpr (OP == V_BICG_XR) {
         double part[3] = {0, 0, 0};
         if (valid) {
@@ -304,8 +304,8 @@ __device__ __forceinline__ void vec_item(const VSeg &a, int item, double *red)
                 part[1] += (double)hv[e].re * sv[e].im - (double)hv[e].im * sv[e].re;
                 part[2] += (double)sv[e].re * sv[e].re + (double)sv[e].im * sv[e].im;
             }
-            store_spinor<S>(a.f[0], Vh, rhs, cb, xv);
-            store_spinor<S>(a.f[1], Vh, rhs, cb, sv);
+            store_spinor<S, true>(a.f[0], Vh, rhs, cb, xv);
+            store_spinor<S, true>(a.f[1], Vh, rhs, cb, sv);
         }
         write_parts<3>(part, red, a.parts, rhs, nb, blk);
     } else if constexpr (OP == V_CG_XR) {
@@ -323,8 +323,8 @@ __device__ __forceinline__ void vec_item(const VSeg &a, int item, double *red)
                 rv[e] = rv[e] - alpha * qv[e];
                 part[0] += (double)rv[e].re * rv[e].re + (double)rv[e].im * rv[e].im;
             }
-            store_spinor<S>(a.f[0], Vh, rhs, cb, xv);
-            store_spinor<S>(a.f[1], Vh, rhs, cb, rv);
+            store_spinor<S, true>(a.f[0], Vh, rhs, cb, xv);
+            store_spinor<S, true>(a.f[1], Vh, rhs, cb, rv);
         }
         write_parts<1>(part, red, a.parts, rhs, nb, blk);
     } else if constexpr (OP == V_CG_P) {
@@ -335,13 +335,13 @@ __device__ __forceinline__ void vec_item(const VSeg &a, int item, double *red)
         load_spinor<S>(a.f[1], Vh, rhs, cb, rv);
 #pragma unroll
         for (int e = 0; e < 12; ++e) pv[e] = rv[e] + beta * pv[e];
-        store_spinor<S>(a.f[0], Vh, rhs, cb, pv);
+        store_spinor<S, true>(a.f[0], Vh, rhs, cb, pv);
     } else if constexpr (OP == V_ZERO) {
         if (!valid) return;
         cx<R> v[12];
 #pragma unroll
         for (int e = 0; e < 12; ++e) v[e] = {R(0), R(0)};
-        store_spinor<S>(a.f[0], Vh, rhs, cb, v);
+        store_spinor<S, true>(a.f[0], Vh, rhs, cb, v);
     } else if constexpr (OP == V_NORM2) {
         double part[1] = {0};
         if (valid) {
@@ -392,7 +392,7 @@ __global__ __launch_bounds__(BS) void copy_kernel(Segs<VSeg> B)
         load_spinor<SS>(a.f[1], a.Vh, rhs, cb, v);
 #pragma unroll
         for (int e = 0; e < 12; ++e) w[e] = {RD(v[e].re), RD(v[e].im)};
-        store_spinor<SD>(a.f[0], a.Vh, rhs, cb, w);
+        store_spinor<SD, true>(a.f[0], a.Vh, rhs, cb, w);
     });
 }
 
@@ -418,8 +418,8 @@ __global__ __launch_bounds__(BS) void fold_kernel(Segs<VSeg> B)
             xv[e].im += (double)lv[e].im;
             lv[e] = {R(0), R(0)};
         }
-        store_spinor<double>(a.f[0], a.Vh, rhs, cb, xv);
-        store_spinor<S>(a.f[1], a.Vh, rhs, cb, lv);
+        store_spinor<double, true>(a.f[0], a.Vh, rhs, cb, xv);
+        store_spinor<S, true>(a.f[1], a.Vh, rhs, cb, lv);
     });
 }
 
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(BS) void sub_kernel(Segs<VSeg> B)
         load_spinor<double>(a.f[2], a.Vh, rhs, cb, bv);
 #pragma unroll
         for (int e = 0; e < 12; ++e) av[e] = av[e] - bv[e];
-        store_spinor<double>(a.f[0], a.Vh, rhs, cb, av);
+        store_spinor<double, true>(a.f[0], a.Vh, rhs, cb, av);
     });
 }
 

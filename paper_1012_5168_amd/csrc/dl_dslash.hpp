@@ -144,7 +144,8 @@ constexpr int nparts_c()
 // x + a * acc (the XPAY family, with x - y in place of x for XMY), plus this
 // site's share of the epilogue's reductions in part[].
 // BUF: read x and y through buffer resources (the LDS-link kernel, whose
-// launcher checks that a right-hand side's field fits one).
+// launcher checks that a right-hand side's field fits one), non-temporal.
+// NT: store the output non-temporal (it is not read again by the launch).
 template <typename S, bool BUF>
 __device__ __forceinline__ void load_site(const Field &f, int Vh, int rhs, int64_t cb, cx<typename Fmt<S>::R> v[12])
 {
@@ -154,7 +155,7 @@ __device__ __forceinline__ void load_site(const Field &f, int Vh, int rhs, int64
         load_spinor<S>(f, Vh, rhs, cb, v);
 }
 
-template <typename S, int EPI, bool BUF = false>
+template <typename S, int EPI, bool BUF = false, bool NT = false>
 __device__ __forceinline__ void epilogue(const DKArgs &a, int rhs, int64_t cb, const cx<typename Fmt<S>::R> acc[12],
                                          double part[], bool valid = true)
 {
@@ -212,7 +213,7 @@ __device__ __forceinline__ void epilogue(const DKArgs &a, int rhs, int64_t cb, c
         for (int e = 0; e < 12; ++e) p0 += (double)o[e].re * o[e].re + (double)o[e].im * o[e].im;
         if (valid) part[0] += p0;
     }
-    if (valid) store_spinor<S, BUF>(a.out, a.g.Vh, rhs, cb, o);
+    if (valid) store_spinor<S, NT>(a.out, a.g.Vh, rhs, cb, o);
 }
 
 // neighbour checkerboard indices (x+, x-, y+, y-, z+, z-, t+, t-) of site
@@ -294,7 +295,7 @@ __device__ __forceinline__ void dslash_item(const DKArgs &a, int L, double *red)
         double part[NP > 0 ? NP : 1];
 #pragma unroll
         for (int k = 0; k < (NP > 0 ? NP : 1); ++k) part[k] = 0.0;
-        if (valid && live[r]) epilogue<S, EPI>(a, rhs[r], cb, acc[r], part);
+        if (valid && live[r]) epilogue<S, EPI, false, true>(a, rhs[r], cb, acc[r], part);
         if constexpr (NP > 0) {
             block_sum<NP>(part, red);
             if (threadIdx.x == 0 && live[r]) {
@@ -446,7 +447,7 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
                     }
                     pin_acc<R>(acc);
                 }
-                epilogue<S, EPI, true>(a, r, cb, acc, part, valid);
+                epilogue<S, EPI, true, true>(a, r, cb, acc, part, valid);
                 if constexpr (NP > 0) {
 #pragma unroll
                     for (int k = 0; k < NP; ++k) part[k] = wave_sum(part[k]);
