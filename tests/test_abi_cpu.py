@@ -137,3 +137,16 @@ def test_product_never_reaches_the_oracle():
     if os.path.exists(lib):
         deps = subprocess.run(["readelf", "-d", lib], capture_output=True, text=True).stdout
         assert "oracle" not in deps
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; asked for more it exits with a message and a nonzero status
+    before touching a device."""
+    import subprocess
+    import sys
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
