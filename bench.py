@@ -92,19 +92,19 @@ def cpu_baseline(w):
     }
 
 
-def tsm_comparison(dl, G, w, L_plain, ms_plain):
+def tsm_comparison(dl, G, w, L_plain, ms_plain, lp_prec=None):
     """Time per loop at fixed statistical error: the truncated solver method (400 low-precision
-    truncated solves in FP16 storage / FP32 arithmetic, 25 CGNR iterations, plus 16 high-precision
-    corrections in FP32 with FP64 reliable updates to 1e-10, undiluted noises) against the plain
-    FP64 estimate of the timed step (24 spin-colour-diluted noises), on the same field.
-    time_to_equal_variance = T_tsm * Var_tsm / Var_plain, per Gamma, averaged over t."""
+    truncated solves in FP16 storage (or lp_prec) / FP32 arithmetic, 25 CGNR iterations, plus 16
+    high-precision corrections in FP32 with FP64 reliable updates to 1e-10, undiluted noises)
+    against the plain FP64 estimate of the timed step (24 spin-colour-diluted noises), on the same
+    field.  time_to_equal_variance = T_tsm * Var_tsm / Var_plain, per Gamma, averaged over t."""
     import numpy as np
     import torch
 
     t = synth_workload("tsm_16x16x16x32")
     gam = [0, 15]
     n_lp, n_hp = 400, 16
-    lpp = dl.solve_params(solver=dl.DL_CGNR, prec=dl.DL_F16, fixed_iters=25)
+    lpp = dl.solve_params(solver=dl.DL_CGNR, prec=dl.DL_F16 if lp_prec is None else lp_prec, fixed_iters=25)
     hpp = dl.solve_params(prec=dl.DL_F32, tol=1e-10, maxiter=1000)
     src = dl.z2_sources(t["noise_seed"], n_lp + n_hp)
     # warm-up on other noises with the same split: every launch shape of the timed call is tuned here
@@ -461,6 +461,8 @@ def main():
     }
     if not args.no_tsm:
         out["tsm"] = tsm_comparison(dl, G, w, L, ms_step)
+        # the same split with the low-precision solves in BF16 storage (coarser mantissa, no scales)
+        out["tsm_bf16_lp"] = tsm_comparison(dl, G, w, L, ms_step, lp_prec=dl.DL_BF16)
         # the same 288 solves with FP32 iterations and FP64 reliable updates to the same 1e-10
         pm = dl.solve_params(prec=dl.DL_F32, tol=1e-10, maxiter=2000)
         dl.loops(G, kappa, src, gam, pm)
