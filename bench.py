@@ -222,6 +222,53 @@ def dslash_sweep(dl, torch, G, copy_gbs):
     return out
 
 
+def differentiation_measurement(dl, torch):
+    """The differentiation row on its workload (24^3 x 48, eps 0.35, kappa 0.148, one spin-colour-
+    diluted noise = 12 right-hand sides, FP64 BiCGStab to 1e-10, Gamma = gamma5 and 1): wall time of
+    the loop estimate, of its kappa derivative (two solves per right-hand side) and of its link
+    gradient (forward and adjoint solves plus the outer-product kernel), each after a warm-up call of
+    the same shape, with the kernel-time split of the gradient call."""
+    import numpy as np
+    import synth
+
+    w = synth.WORKLOADS["grad_24x24x24x48"]
+    dims, kappa = w["dims"], w["kappa"]
+    U = synth.gauge_field(dims, w["eps"], w["gauge_seed"])
+    G = dl.Gauge(dl.Lattice(dims, 1), U, precs=(dl.DL_F64,), recon=12)
+    src = dl.z2_sources(w["noise_seed"], 1, scheme=dl.DL_DIL_SPIN_COLOUR)
+    gam = [15, 0]
+    prm = dl.solve_params(tol=1e-10, maxiter=2000)
+    W = np.ones((len(gam), dims[3]), dtype=np.complex128)
+    calls = {
+        "loops": lambda: dl.loops(G, kappa, src, gam, prm),
+        "dkappa": lambda: dl.loops_dkappa(G, kappa, src, gam, prm),
+        "link_grad": lambda: dl.loops_link_grad(G, kappa, src, gam, W, prm),
+    }
+    out = {"workload": "24^3x48, kappa 0.148, 1 spin-colour-diluted noise (12 RHS), FP64 to 1e-10"}
+    for name, f in calls.items():
+        f()
+        torch.cuda.synchronize()
+        if name == "link_grad":
+            dl.dl_profile_enable(True)
+        t0 = time.perf_counter()
+        r = f()
+        torch.cuda.synchronize()
+        out["ms_" + name] = round((time.perf_counter() - t0) * 1e3, 2)
+        st = r[-1]
+        assert all(x[0] == dl.DL_OK for x in st), name
+    kinds = {"dslash": 0, "krylov_vectors": 1, "sources_traces_gradient": 2}
+    split = {}
+    for k, v in kinds.items():
+        n, ms, by = dl.dl_profile_read(v)
+        split[k] = {"ms": round(ms, 2), "gbs": round(by / (ms * 1e-3) / 1e9, 1) if ms > 0 else None}
+    dl.dl_profile_enable(False)
+    out["link_grad_kernel_split"] = split
+    out["dkappa_vs_loops"] = round(out["ms_dkappa"] / out["ms_loops"], 3)
+    out["link_grad_vs_loops"] = round(out["ms_link_grad"] / out["ms_loops"], 3)
+    del G
+    return out
+
+
 def dilution_study(dl, G, w, n_noise=16):
     """The error-versus-inversions comparison of dilution schemes (Section 4, on the synthetic field):
     for each scheme, n_noise noises give per-noise estimates e_n of the time-averaged loop
@@ -479,6 +526,7 @@ def main():
         out["copy_reference_gbs"] = round(cg, 1)
         out["roofline"]["frac_of_copy"] = round(plain_gbs / cg, 4)
         out["dslash_by_precision"] = dslash_sweep(dl, torch, G, cg)
+        out["differentiation"] = differentiation_measurement(dl, torch)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}

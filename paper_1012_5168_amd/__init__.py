@@ -513,14 +513,24 @@ def loops_link_grad(gauge: Gauge, kappa: float, sources: dl_sources, gammas, w, 
         w = np.broadcast_to(w, (n,) + w.shape)
     w = w.reshape(n, len(gammas), T)
     wb = np.stack([w.real, w.imag], axis=-1)
-    grad = np.zeros((4, V, 3, 3, 2), dtype=np.float64)
+    grad = _pinned_host((4, V, 3, 3, 2))
     loops = np.zeros((n, len(gammas), T, 2), dtype=np.float64)
     dk = np.zeros((n, len(gammas), T, 2), dtype=np.float64) if with_dkappa else None
     nrhs = dl_sources_count(gauge.lattice.h, sources)
     st = (dl_solve_stats * (3 * nrhs))()
     dl_loops_link_grad(gauge.h, kappa, sources, params, gammas, wb, grad, loops, dk, st, stream)
-    z = lambda a: None if a is None else a[..., 0] + 1j * a[..., 1]  # noqa: E731
+    # (re, im) pairs read as complex numbers in place
+    z = lambda a: None if a is None else a.view(np.complex128)[..., 0]  # noqa: E731
     return z(grad), z(loops), z(dk), _stats_list(st)
+
+
+def _pinned_host(shape):
+    """An FP64 host array in page-locked memory (allocated as such, never registered after the fact):
+    the library's device-to-host copy into it is a direct transfer, without staging or first-touch
+    page faults.  The array keeps its torch storage alive."""
+    import torch
+
+    return torch.empty(shape, dtype=torch.float64, pin_memory=True).numpy()
 
 
 def batch_loops(gauges, kappas, sources, gammas, params=None, stream=None):
