@@ -491,6 +491,7 @@ def main():
         "kernel_gbs": {
             "dslash": round(dslash_gbs, 1),
             "krylov_vectors": round(by_b / (ms_b * 1e-3) / 1e9, 1),
+            "sources_traces": round(by_t / (ms_t * 1e-3) / 1e9, 1) if ms_t > 0 else None,
         },
         "roofline": {
             "kernel": kernel_name(cfg),
