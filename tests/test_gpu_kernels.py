@@ -5,7 +5,8 @@ autotuner prefers on the day.
 
 Shapes are chosen so that a 64-site block and the region walk have ragged
 ends: 6x4x6x10 has 720 sites per parity (11 full blocks and a 16-site tail),
-and odd right-hand-side counts leave wavefronts of the LDS kernel idle.
+and odd right-hand-side counts leave wavefronts of the LDS kernel idle; 300
+right-hand sides take every wavefront count over more than one 64-lane chunk.
 
 Tolerances are those of the parity suite: FP64 operators 1e-13 of max |ref|,
 FP32 2e-6, FP16 4e-3, BF16 3e-2; FP64 solves to 1e-12 checked with the
@@ -161,3 +162,46 @@ def test_batch_segments_both_kernels(dl, dev, kernel):
         assert all(s[0] == dl.DL_OK for s in st)
         L1, _ = dl.loops(G, kap, src, [0, 15], prm)
         assert np.max(np.abs(L1 - L)) <= 1e-10 * np.max(np.abs(L1)), (kernel, np.max(np.abs(L1 - L)))
+
+
+def test_many_rhs_chunks_both_kernels(dl, dev, kernel):
+    """300 right-hand sides: more than one 64-lane chunk of every wavefront count (64 x 4 = 256
+    at most), with a ragged last chunk.  The hopping term of all 300 equals the oracle's; then
+    BiCGStab on sources of five kinds (random, scaled, point, one timeslice, two spins), which
+    converge at different iterations, so that right-hand sides of later chunks stop while
+    those of the first still iterate: every solution meets the oracle's operator residual."""
+    dims = (6, 4, 6, 10)
+    n = 300
+    U = synth.gauge_field(dims, 0.3, seed=371)  # a rough field near the critical kappa: ~50 iterations
+    kappa = 0.15
+    lat = dl.Lattice(dims, 1)
+    G = dl.Gauge(lat, U)
+    b = synth.random_spinor(dims, n, seed=372)
+    V = int(np.prod(dims))
+    tsl = np.arange(V) // (dims[0] * dims[1] * dims[2])
+    for r in range(n):
+        kind = r % 5
+        if kind == 1:
+            b[r] *= 1e-3
+        elif kind == 2:
+            site, sc = (37 * r) % V, r % 12
+            b[r] = 0
+            b[r, site, sc // 3, sc % 3] = 1.0 - 0.5j
+        elif kind == 3:
+            b[r][tsl != r % dims[3]] = 0
+        elif kind == 4:
+            b[r, :, 2:] = 0
+    x = to_dev(b, dev)
+    out = from_dev(dl.apply(G, kappa, dl.DL_OP_DHOP, x))
+    for r in range(n):
+        ref = oracle.dhop(U, b[r], dims, 1)
+        err = np.max(np.abs(out[r] - ref))
+        assert err <= 1e-13 * np.max(np.abs(ref)), (kernel, r, err)
+    sol, st = dl.solve(G, kappa, x, dl.solve_params(tol=1e-12, maxiter=2000))
+    sol = from_dev(sol)
+    assert len({s[1] for s in st}) >= 3, (kernel, sorted({s[1] for s in st}))
+    for r in range(n):
+        status, iters, upd, res = st[r]
+        assert status == dl.DL_OK and res <= 1e-12, (kernel, r, st[r])
+        rr = np.linalg.norm(b[r] - oracle.apply_m(U, sol[r], dims, kappa)) / np.linalg.norm(b[r])
+        assert rr <= 1.5e-12, (kernel, r, rr)
