@@ -49,6 +49,10 @@ def parse():
                     help="instead of the timed step: the batched workload (8^3x16, 12^3x24, 16^3x32, 768 "
                          "right-hand sides each, FP32 iterations with FP64 reliable updates) with and without "
                          "graph replay")
+    ap.add_argument("--differentiation", action="store_true",
+                    help="instead of the timed step: the differentiation workload (24^3x48, 384 right-hand sides, "
+                         "FP32 iterations with FP64 reliable updates; loops, their kappa derivative and their "
+                         "link gradient)")
     ap.add_argument("--sweep-only", action="store_true",
                     help="instead of the timed step: only the per-precision hopping-kernel sweep and the "
                          "single-right-hand-side figures")
@@ -222,29 +226,32 @@ def dslash_sweep(dl, torch, G, copy_gbs):
     return out
 
 
-def differentiation_measurement(dl, torch):
-    """The differentiation row on its workload (24^3 x 48, eps 0.35, kappa 0.148, one spin-colour-
-    diluted noise = 12 right-hand sides, FP64 BiCGStab to 1e-10, Gamma = gamma5 and 1): wall time of
-    the loop estimate, of its kappa derivative (two solves per right-hand side) and of its link
-    gradient (forward and adjoint solves plus the outer-product kernel), each after a warm-up call of
-    the same shape, with the kernel-time split of the gradient call."""
+def differentiation_measurement(dl, torch, n_noise=32):
+    """The differentiation row on its workload (24^3 x 48, eps 0.35, kappa 0.148, 32 spin-colour-
+    diluted complex-Z2 noises = 384 right-hand sides, FP32 iterations with FP64 reliable updates to
+    1e-10, Gamma = gamma5 and 1): wall time of the loop estimate, of its kappa derivative (two solves
+    per right-hand side) and of its link gradient (forward and adjoint solves plus the outer-product
+    kernel), each after a warm-up call of the same shape, with the kernel-time split of the gradient
+    call."""
     import numpy as np
     import synth
 
     w = synth.WORKLOADS["grad_24x24x24x48"]
     dims, kappa = w["dims"], w["kappa"]
     U = synth.gauge_field(dims, w["eps"], w["gauge_seed"])
-    G = dl.Gauge(dl.Lattice(dims, 1), U, precs=(dl.DL_F64,), recon=12)
-    src = dl.z2_sources(w["noise_seed"], 1, scheme=dl.DL_DIL_SPIN_COLOUR)
+    G = dl.Gauge(dl.Lattice(dims, 1), U, precs=(dl.DL_F64, dl.DL_F32), recon=12)
+    src = dl.z2_sources(w["noise_seed"], n_noise, scheme=dl.DL_DIL_SPIN_COLOUR)
+    nrhs = dl.dl_sources_count(G.lattice.h, src)
     gam = [15, 0]
-    prm = dl.solve_params(tol=1e-10, maxiter=2000)
+    prm = dl.solve_params(prec=dl.DL_F32, tol=1e-10, maxiter=2000)
     W = np.ones((len(gam), dims[3]), dtype=np.complex128)
     calls = {
         "loops": lambda: dl.loops(G, kappa, src, gam, prm),
         "dkappa": lambda: dl.loops_dkappa(G, kappa, src, gam, prm),
         "link_grad": lambda: dl.loops_link_grad(G, kappa, src, gam, W, prm),
     }
-    out = {"workload": "24^3x48, kappa 0.148, 1 spin-colour-diluted noise (12 RHS), FP64 to 1e-10"}
+    out = {"workload": "24^3x48, kappa 0.148, %d spin-colour-diluted noises (%d RHS), FP32 iterations with FP64 "
+                       "reliable updates to 1e-10" % (n_noise, nrhs)}
     for name, f in calls.items():
         f()
         torch.cuda.synchronize()
@@ -253,9 +260,10 @@ def differentiation_measurement(dl, torch):
         t0 = time.perf_counter()
         r = f()
         torch.cuda.synchronize()
-        out["ms_" + name] = round((time.perf_counter() - t0) * 1e3, 2)
+        out["ms_" + name] = round((time.perf_counter() - t0) * 1e3, 1)
         st = r[-1]
         assert all(x[0] == dl.DL_OK for x in st), name
+        out["ms_per_rhs_" + name] = round(out["ms_" + name] / nrhs, 3)
     kinds = {"dslash": 0, "krylov_vectors": 1, "sources_traces_gradient": 2}
     split = {}
     for k, v in kinds.items():
@@ -413,6 +421,10 @@ def main():
     if args.batch:
         del G
         print(json.dumps(batch_measurement(dl, torch)), flush=True)
+        return
+    if args.differentiation:
+        del G
+        print(json.dumps(differentiation_measurement(dl, torch)), flush=True)
         return
     if args.sweep_only:
         cg = copy_rate(torch)  # its copies (2 GiB read, 2 GiB written) also serve as the counters' reference
