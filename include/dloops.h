@@ -159,7 +159,7 @@ typedef struct {
     int32_t maxiter;     /* iteration cap (tolerance-driven solves) */
     int32_t fixed_iters; /* > 0: run exactly this many iterations from x0 = 0 (truncated solve) */
     double delta;        /* reliable-update trigger: |r| < delta * max |r| since the last update
-                            (0 -> 0.1) */
+                            (0 -> 0.01) */
     int32_t poll;        /* iterations between host convergence checks (0 -> automatic) */
     int32_t use_graph;   /* 1: capture `poll` BiCGStab iterations once as a hipGraph and replay it
                             (the first chunk runs eagerly and tunes the launch shapes) */

@@ -854,7 +854,7 @@ void bicgstab_multi(const std::vector<Prob> &P0, const dl_solve_params &prm, hip
     for (Prob &p : P) p.c.s = s;
     const int prec = P[0].w->prec;
     const bool mixed = prec != P64;
-    const double delta = mixed ? (prm.delta > 0 ? prm.delta : 0.1) : 0.0;
+    const double delta = mixed ? (prm.delta > 0 ? prm.delta : 0.01) : 0.0;
     auto upd = [](const Prob &p) { return (const int *)p.w->upd.as<int>(); };
 
     // |b|^2 over both parities; bhat = b_e + kappa D_eo b_o
