@@ -202,12 +202,19 @@ __global__ void gamma_contract_kernel(const double *C, int ncls, int T, const do
 //   out(x) = [ in(x) + alpha sum_{i=x,y,z} ( U_i(x) in(x+i) + U_i(x-i)^+ in(x-i) ) ] / (1 + 6 alpha),
 // spin-diagonal (the same colour multiply on all four spins), no boundary
 // sign (space is periodic).  FP64 fields and links.
+// One workgroup per (block of BS sites, right-hand side).  Workgroup b runs on
+// XCD b mod 8; each XCD takes a contiguous eighth of the (site block, RHS)
+// items with the RHS running fastest, so the right-hand sides of a site block
+// run together on one XCD and its links are fetched into that L2 once.
 template <int NE>
 __global__ __launch_bounds__(BS) void smear_kernel(const void *links, Field in_same, Field in_other, Field out,
-                                                   int parity, Geom g, double alpha, double norm)
+                                                   int parity, Geom g, double alpha, double norm, int nrhs)
 {
-    const int rhs = blockIdx.y;
-    const int cb = blockIdx.x * BS + threadIdx.x;
+    const int64_t total = (int64_t)gridDim.x;
+    const int xcd = blockIdx.x % 8;
+    const int64_t item = xcd * (total / 8) + min<int64_t>(xcd, total % 8) + blockIdx.x / 8;
+    const int rhs = (int)(item % nrhs);
+    const int cb = (int)(item / nrhs) * BS + threadIdx.x;
     if (cb >= g.Vh) return;
     const int p = parity, q = 1 - p;
     const Site s = decode(g, cb, p);
@@ -486,13 +493,28 @@ void k_smear(const void *links, int recon, Field ine, Field ino, Field oute, Fie
     // links of the three spatial directions, both parities, once
     ProfScope ps(PROF_SMEAR, 6 * field_bytes(P64, g.Vh, nrhs) + 2.0 * 3 * g.Vh * (recon == 12 ? 6 : 9) * 16, s);
     const double norm = 1.0 / (1.0 + 6.0 * alpha);
-    dim3 grid((g.Vh + BS - 1) / BS, nrhs);
-    if (recon == 12) {
-        hipLaunchKernelGGL(smear_kernel<6>, grid, dim3(BS), 0, s, links, ine, ino, oute, 0, g, alpha, norm);
-        hipLaunchKernelGGL(smear_kernel<6>, grid, dim3(BS), 0, s, links, ino, ine, outo, 1, g, alpha, norm);
-    } else {
-        hipLaunchKernelGGL(smear_kernel<9>, grid, dim3(BS), 0, s, links, ine, ino, oute, 0, g, alpha, norm);
-        hipLaunchKernelGGL(smear_kernel<9>, grid, dim3(BS), 0, s, links, ino, ine, outo, 1, g, alpha, norm);
+    // one workgroup per (site block, RHS), the kernel maps them to XCDs; the
+    // right-hand sides go in chunks that keep the grid below 2^31 workgroups
+    const int64_t nblk = (g.Vh + BS - 1) / BS;
+    const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(nrhs, 0x7fffffff / nblk));
+    for (int r0 = 0; r0 < nrhs; r0 += chunk) {
+        const int n = std::min(chunk, nrhs - r0);
+        auto sub = [&](Field f) {  // FP64 fields: [rhs][12][Vh] complex, no scales
+            f.d = static_cast<char *>(f.d) + (size_t)r0 * 12 * g.Vh * 16;
+            return f;
+        };
+        const dim3 grid((unsigned)(nblk * n));
+        if (recon == 12) {
+            hipLaunchKernelGGL(smear_kernel<6>, grid, dim3(BS), 0, s, links, sub(ine), sub(ino), sub(oute), 0, g,
+                               alpha, norm, n);
+            hipLaunchKernelGGL(smear_kernel<6>, grid, dim3(BS), 0, s, links, sub(ino), sub(ine), sub(outo), 1, g,
+                               alpha, norm, n);
+        } else {
+            hipLaunchKernelGGL(smear_kernel<9>, grid, dim3(BS), 0, s, links, sub(ine), sub(ino), sub(oute), 0, g,
+                               alpha, norm, n);
+            hipLaunchKernelGGL(smear_kernel<9>, grid, dim3(BS), 0, s, links, sub(ino), sub(ine), sub(outo), 1, g,
+                               alpha, norm, n);
+        }
     }
 }
 
