@@ -150,3 +150,19 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode != 0
     assert "one GPU" in r.stderr
     assert r.stdout.strip() == ""
+
+
+def test_bench_cpu_only_reports_the_oracle_baseline():
+    """`bench.py --cpu-only` times the oracle on its bounded sample (one hopping-term application
+    and one FP64 solve to 1e-10 on 16^3 x 32) without a GPU and prints the cpu_baseline object."""
+    import json
+    import subprocess
+    import sys
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--cpu-only"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    assert d["kind"] == "oracle" and d["unit"] == "GB/s"
+    assert d["value"] > 0 and d["cores"] >= 1 and d["seconds_per_solve"] > 0
+    assert "16^3x32" in d["sample"] and "1e-10" in d["sample"]
