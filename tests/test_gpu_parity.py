@@ -260,3 +260,37 @@ def test_full_size_loops_batch_properties(dl, dev):
     tot = L.sum(axis=2)
     assert np.max(np.abs(tot.imag)) < 1e-8 * np.max(np.abs(tot.real))
     assert np.max(np.abs(L.imag)) > 1e-3  # per timeslice the imaginary parts do not vanish
+
+
+def test_zero_and_empty_right_hand_sides(dl, dev):
+    """Degenerate inputs: a zero right-hand side among others solves to x = 0 in no iterations with
+    status OK (BiCGStab in FP64 and in FP32 with FP64 reliable updates, and the truncated CGNR),
+    while its neighbours in the batch still meet the oracle's operator residual; an empty batch is
+    refused with an error."""
+    dims = (4, 4, 6, 8)
+    U = synth.gauge_field(dims, 0.5, seed=391)
+    kappa = 0.12
+    G = dl.Gauge(dl.Lattice(dims, 1), U, precs=(dl.DL_F64, dl.DL_F32, dl.DL_F16))
+    b = synth.random_spinor(dims, 3, seed=392)
+    b[1] = 0
+    for prm in (dl.solve_params(tol=1e-12, maxiter=500), dl.solve_params(prec=dl.DL_F32, tol=1e-10, maxiter=1000)):
+        x, st = dl.solve(G, kappa, to_dev(b, dev), prm)
+        x = from_dev(x)
+        assert st[1][0] == dl.DL_OK and st[1][1] == 0 and st[1][3] == 0.0, st[1]
+        assert np.all(x[1] == 0)
+        for r in (0, 2):
+            assert st[r][0] == dl.DL_OK, st[r]
+            rr = np.linalg.norm(b[r] - oracle.apply_m(U, x[r], dims, kappa)) / np.linalg.norm(b[r])
+            assert rr <= 1.5 * prm.tol, (r, rr)
+    x, st = dl.solve(G, kappa, to_dev(b, dev), dl.solve_params(solver=dl.DL_CGNR, prec=dl.DL_F16, fixed_iters=25))
+    x = from_dev(x)
+    assert np.all(x[1] == 0) and st[1][0] == dl.DL_OK
+    for r in (0, 2):
+        ref = oracle.solve_lp(U, b[r], dims, kappa, niter=25)
+        assert np.linalg.norm(x[r] - ref) / np.linalg.norm(ref) < 3e-2
+    V = int(np.prod(dims))
+    empty = torch.zeros((0, V, 4, 3), dtype=torch.complex128, device=dev)
+    with pytest.raises(dl.DLError):
+        dl.solve(G, kappa, empty)
+    with pytest.raises(dl.DLError):
+        dl.apply(G, kappa, dl.DL_OP_DHOP, empty)
