@@ -271,9 +271,9 @@ __device__ __forceinline__ void vec_item(const VSeg &a, int item, double *red)
         if (!valid) return;
         const cx<R> beta = ld_c<R>(a.st[rhs].beta), omega = ld_c<R>(a.st[rhs].omega);
         cx<R> pv[12], rv[12], vv[12];
-        load_spinor<S>(a.f[0], Vh, rhs, cb, pv);
-        load_spinor<S>(a.f[1], Vh, rhs, cb, rv);
-        load_spinor<S>(a.f[2], Vh, rhs, cb, vv);
+        load_spinor<S, true>(a.f[0], Vh, rhs, cb, pv);
+        load_spinor<S, true>(a.f[1], Vh, rhs, cb, rv);
+        load_spinor<S, true>(a.f[2], Vh, rhs, cb, vv);
 #pragma unroll
         for (int e = 0; e < 12; ++e) pv[e] = rv[e] + beta * (pv[e] - omega * vv[e]);
         store_spinor<S, true>(a.f[0], Vh, rhs, cb, pv);
@@ -281,8 +281,8 @@ __device__ __forceinline__ void vec_item(const VSeg &a, int item, double *red)
         if (!valid) return;
         const cx<R> alpha = ld_c<R>(a.st[rhs].alpha);
         cx<R> rv[12], vv[12];
-        load_spinor<S>(a.f[0], Vh, rhs, cb, rv);
-        load_spinor<S>(a.f[1], Vh, rhs, cb, vv);
+        load_spinor<S, true>(a.f[0], Vh, rhs, cb, rv);
+        load_spinor<S, true>(a.f[1], Vh, rhs, cb, vv);
 #pragma unroll
         for (int e = 0; e < 12; ++e) rv[e] = rv[e] - alpha * vv[e];
         store_spinor<S, true>(a.f[0], Vh, rhs, cb, rv);
@@ -291,11 +291,11 @@ __device__ __forceinline__ void vec_item(const VSeg &a, int item, double *red)
         if (valid) {
             const cx<R> alpha = ld_c<R>(a.st[rhs].alpha), omega = ld_c<R>(a.st[rhs].omega);
             cx<R> xv[12], sv[12], pv[12], tv[12], hv[12];
-            load_spinor<S>(a.f[0], Vh, rhs, cb, xv);
-            load_spinor<S>(a.f[1], Vh, rhs, cb, sv);
-            load_spinor<S>(a.f[2], Vh, rhs, cb, pv);
-            load_spinor<S>(a.f[3], Vh, rhs, cb, tv);
-            load_spinor<S>(a.f[4], Vh, rhs, cb, hv);
+            load_spinor<S, true>(a.f[0], Vh, rhs, cb, xv);
+            load_spinor<S, true>(a.f[1], Vh, rhs, cb, sv);
+            load_spinor<S, true>(a.f[2], Vh, rhs, cb, pv);
+            load_spinor<S, true>(a.f[3], Vh, rhs, cb, tv);
+            load_spinor<S, true>(a.f[4], Vh, rhs, cb, hv);
 #pragma unroll
             for (int e = 0; e < 12; ++e) {
                 xv[e] = xv[e] + alpha * pv[e] + omega * sv[e];
@@ -313,10 +313,10 @@ __device__ __forceinline__ void vec_item(const VSeg &a, int item, double *red)
         if (valid) {
             const R alpha = R(a.st[rhs].alpha[0]);
             cx<R> xv[12], rv[12], pv[12], qv[12];
-            load_spinor<S>(a.f[0], Vh, rhs, cb, xv);
-            load_spinor<S>(a.f[1], Vh, rhs, cb, rv);
-            load_spinor<S>(a.f[2], Vh, rhs, cb, pv);
-            load_spinor<S>(a.f[3], Vh, rhs, cb, qv);
+            load_spinor<S, true>(a.f[0], Vh, rhs, cb, xv);
+            load_spinor<S, true>(a.f[1], Vh, rhs, cb, rv);
+            load_spinor<S, true>(a.f[2], Vh, rhs, cb, pv);
+            load_spinor<S, true>(a.f[3], Vh, rhs, cb, qv);
 #pragma unroll
             for (int e = 0; e < 12; ++e) {
                 xv[e] = xv[e] + alpha * pv[e];
@@ -331,8 +331,8 @@ __device__ __forceinline__ void vec_item(const VSeg &a, int item, double *red)
         if (!valid) return;
         const R beta = R(a.st[rhs].beta[0]);
         cx<R> pv[12], rv[12];
-        load_spinor<S>(a.f[0], Vh, rhs, cb, pv);
-        load_spinor<S>(a.f[1], Vh, rhs, cb, rv);
+        load_spinor<S, true>(a.f[0], Vh, rhs, cb, pv);
+        load_spinor<S, true>(a.f[1], Vh, rhs, cb, rv);
 #pragma unroll
         for (int e = 0; e < 12; ++e) pv[e] = rv[e] + beta * pv[e];
         store_spinor<S, true>(a.f[0], Vh, rhs, cb, pv);
@@ -346,7 +346,7 @@ __device__ __forceinline__ void vec_item(const VSeg &a, int item, double *red)
         double part[1] = {0};
         if (valid) {
             cx<R> v[12];
-            load_spinor<S>(a.f[0], Vh, rhs, cb, v);
+            load_spinor<S, true>(a.f[0], Vh, rhs, cb, v);
 #pragma unroll
             for (int e = 0; e < 12; ++e) part[0] += (double)v[e].re * v[e].re + (double)v[e].im * v[e].im;
         }
@@ -355,8 +355,8 @@ __device__ __forceinline__ void vec_item(const VSeg &a, int item, double *red)
         double part[2] = {0, 0};
         if (valid) {
             cx<R> av[12], bv[12];
-            load_spinor<S>(a.f[0], Vh, rhs, cb, av);
-            load_spinor<S>(a.f[1], Vh, rhs, cb, bv);
+            load_spinor<S, true>(a.f[0], Vh, rhs, cb, av);
+            load_spinor<S, true>(a.f[1], Vh, rhs, cb, bv);
 #pragma unroll
             for (int e = 0; e < 12; ++e) {
                 part[0] += (double)av[e].re * bv[e].re + (double)av[e].im * bv[e].im;

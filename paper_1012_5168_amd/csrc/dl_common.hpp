@@ -248,7 +248,8 @@ struct Field {
     float *nrm;    // [nrhs][Vh] per-site scale (FP16 only, else null)
 };
 
-template <typename S>
+// NT: non-temporal loads (data the kernel reads once)
+template <typename S, bool NT = false>
 __device__ __forceinline__ void load_spinor(const Field &f, int64_t Vh, int rhs, int64_t cb,
                                             cx<typename Fmt<S>::R> v[12])
 {
@@ -257,9 +258,19 @@ __device__ __forceinline__ void load_spinor(const Field &f, int64_t Vh, int rhs,
     constexpr int V = F::VEC;
     const typename F::E *p = static_cast<const typename F::E *>(f.d) + (int64_t)rhs * 12 * Vh;
 #pragma unroll
-    for (int j = 0; j < 12 / V; ++j) F::ldv(p, (int64_t)j * Vh + cb, v + j * V);
+    for (int j = 0; j < 12 / V; ++j) {
+        if constexpr (NT) {
+            using U4 = unsigned __attribute__((ext_vector_type(4)));
+            const U4 raw = __builtin_nontemporal_load(reinterpret_cast<const U4 *>(p) + ((int64_t)j * Vh + cb));
+            uint4 q;
+            __builtin_memcpy(&q, &raw, 16);
+            F::unpack(q, v + j * V);
+        } else {
+            F::ldv(p, (int64_t)j * Vh + cb, v + j * V);
+        }
+    }
     if constexpr (F::scaled) {
-        R s = f.nrm[(int64_t)rhs * Vh + cb];
+        R s = NT ? __builtin_nontemporal_load(f.nrm + (int64_t)rhs * Vh + cb) : f.nrm[(int64_t)rhs * Vh + cb];
 #pragma unroll
         for (int e = 0; e < 12; ++e) v[e] = s * v[e];
     }
