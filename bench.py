@@ -102,6 +102,136 @@ def cpu_baseline(w, n_apply=10, n_solve=3):
     }
 
 
+def tsm_comparison(dl, G, w, L_plain, ms_plain, lp_prec=None):
+    """Time per loop at fixed statistical error: the truncated solver method (400 low-precision
+    truncated solves in FP16 storage (or lp_prec) / FP32 arithmetic, 25 CGNR iterations, plus 16
+    high-precision corrections in FP32 with FP64 reliable updates to 1e-10, undiluted noises)
+    against the plain FP64 estimate of the timed step (24 spin-colour-diluted noises), on the same
+    field.  time_to_equal_variance = T_tsm * Var_tsm / Var_plain, per Gamma, averaged over t."""
+    import numpy as np
+    import torch
+
+    t = synth_workload("tsm_16x16x16x32")
+    gam = [0, 15]
+    n_lp, n_hp = 400, 16
+    lpp = dl.solve_params(solver=dl.DL_CGNR, prec=dl.DL_F16 if lp_prec is None else lp_prec, fixed_iters=25)
+    hpp = dl.solve_params(prec=dl.DL_F32, tol=1e-10, maxiter=1000)
+    src = dl.z2_sources(t["noise_seed"], n_lp + n_hp)
+    # warm-up on other noises with the same split: every launch shape of the timed call is tuned here
+    dl.loops_tsm(G, t["kappa"], dl.z2_sources(t["noise_seed"] + 7, n_lp + n_hp), n_lp, n_hp, gam, lpp, hpp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a, b, c, st = dl.loops_tsm(G, t["kappa"], src, n_lp, n_hp, gam, lpp, hpp)
+    torch.cuda.synchronize()
+    ms_tsm = (time.perf_counter() - t0) * 1e3
+    est, var_t = dl.tsm_estimate(a, b, c)
+    var_p = np.var(L_plain, axis=0, ddof=1) / len(L_plain)
+    out = {"ms_tsm": round(ms_tsm, 2), "ms_plain": round(ms_plain, 2), "n_lp": n_lp, "n_hp": n_hp,
+           "hp_converged": all(x[0] == dl.DL_OK for x in st[(n_lp + n_hp):])}
+    # bootstrap over noises (LP set, HP set and the plain estimate's noises resampled independently)
+    rng = np.random.default_rng(12345)
+    nboot = 400
+    ratios = np.empty((nboot, len(gam)))
+    for i in range(nboot):
+        il = rng.integers(0, n_lp, n_lp)
+        ih = rng.integers(0, n_hp, n_hp)
+        ip = rng.integers(0, len(L_plain), len(L_plain))
+        _, vtb = dl.tsm_estimate(a[il], b[ih], c[ih])
+        vpb = np.var(L_plain[ip], axis=0, ddof=1) / len(L_plain)
+        ratios[i] = [np.mean(vtb[k].real) / np.mean(vpb[k].real) * ms_tsm / ms_plain for k in range(len(gam))]
+    for k, g in enumerate(gam):
+        vt = float(np.mean(var_t[k].real))
+        vp = float(np.mean(var_p[k].real))
+        lo, hi = np.percentile(ratios[:, k], [16, 84])
+        out["gamma%d" % g] = {
+            "var_tsm": vt, "var_plain": vp,
+            "time_to_equal_variance_ms": round(ms_tsm * vt / vp, 2),
+            "ratio_vs_plain": round(ms_tsm * vt / (vp * ms_plain), 4),
+            "ratio_bootstrap_68": [round(float(lo), 4), round(float(hi), 4)],
+        }
+    return out
+
+
+def copy_rate(torch):
+    """Achievable HBM rate of a plain device copy: 2 GiB read + 2 GiB written, event-timed."""
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    del a, b
+    return 2 * 8 * n / (ms * 1e-3) / 1e9
+
+
+def hop_rate(dl, torch, G, nrhs, prec, reps=3):
+    """Plain half-dslash launches of D applied to nrhs right-hand sides at one storage precision:
+    (launches, algorithmic GB/s, mean event-timed launch in us, launch configuration).  The first
+    application tunes; the profiled ones follow."""
+    V = G.lattice.V
+    x = torch.zeros((nrhs, V, 4, 3), dtype=torch.complex128, device="cuda")
+    x.real.normal_()
+    dl.apply(G, 0.15, dl.DL_OP_DHOP, x, prec=prec)
+    torch.cuda.synchronize()
+    dl.dl_profile_enable(True)
+    for _ in range(reps):
+        dl.apply(G, 0.15, dl.DL_OP_DHOP, x, prec=prec)
+    torch.cuda.synchronize()
+    n, ms, by = dl.dl_profile_read(3)
+    cfg = dl.dl_profile_config(3)
+    dl.dl_profile_enable(False)
+    del x
+    torch.cuda.empty_cache()
+    return n, by / (ms * 1e-3) / 1e9, ms / max(n, 1) * 1e3, cfg
+
+
+def dslash_sweep(dl, torch, G, copy_gbs):
+    """The plain half dslash D_oe / D_eo at every storage precision on the timed workload's batch
+    (16^3 x 32, 288 right-hand sides), the single-right-hand-side FP64 figure on the same lattice
+    (its 75 MB working set sits in the 256 MB Infinity Cache), and the single-right-hand-side FP64
+    figure on 24^3 x 48 (382 MB, larger than that cache)."""
+    import synth
+
+    out = {}
+    names = {dl.DL_F64: "f64", dl.DL_F32: "f32", dl.DL_F16: "f16", dl.DL_BF16: "bf16"}
+    for prec, nm in names.items():
+        n, gbs, us, cfg = hop_rate(dl, torch, G, 288, prec)
+        out[nm + "_288rhs"] = {"gbs": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                               "frac_copy": round(gbs / copy_gbs, 4), "avg_launch_us": round(us, 1),
+                               "launches": n, "config": list(cfg)}
+    n, gbs, us, cfg = hop_rate(dl, torch, G, 1, dl.DL_F64, reps=20)
+    out["f64_1rhs_cache_resident"] = {"gbs": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                                      "avg_launch_us": round(us, 1), "launches": n, "config": list(cfg)}
+    w = synth.WORKLOADS["grad_24x24x24x48"]
+    U = synth.gauge_field(w["dims"], w["eps"], w["gauge_seed"])
+    G2 = dl.Gauge(dl.Lattice(w["dims"], 1), U, precs=(dl.DL_F64,), recon=12)
+    n, gbs, us, cfg = hop_rate(dl, torch, G2, 1, dl.DL_F64, reps=20)
+    out["f64_1rhs_24x24x24x48"] = {"gbs": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                                   "frac_copy": round(gbs / copy_gbs, 4), "avg_launch_us": round(us, 1),
+                                   "launches": n, "config": list(cfg)}
+    del G2
+    # one smearing step on 24 right-hand sides (FP64, 12-parameter links), profile kind 4
+    x = torch.zeros((24, G.lattice.V, 4, 3), dtype=torch.complex128, device="cuda")
+    x.real.normal_()
+    dl.smear(G, 0.5, 2, x)
+    torch.cuda.synchronize()
+    dl.dl_profile_enable(True)
+    dl.smear(G, 0.5, 10, x)
+    torch.cuda.synchronize()
+    n, ms, by = dl.dl_profile_read(4)
+    dl.dl_profile_enable(False)
+    del x
+    out["smear_f64_24rhs"] = {"gbs": round(by / (ms * 1e-3) / 1e9, 1), "frac_hbm_peak": round(by / (ms * 1e-3) / 1e9
+                                                                                               / HBM_PEAK_GBS, 4),
+                              "avg_step_us": round(ms / max(n, 1) * 1e3, 1), "steps": n}
+    return out
+
+
 def differentiation_measurement(dl, torch, n_noise=32):
     """The differentiation row on its workload (24^3 x 48, eps 0.35, kappa 0.148, 32 spin-colour-
     diluted complex-Z2 noises = 384 right-hand sides, FP32 iterations with FP64 reliable updates to

@@ -166,3 +166,23 @@ def test_bench_cpu_only_reports_the_oracle_baseline():
     assert d["kind"] == "oracle" and d["unit"] == "GB/s"
     assert d["value"] > 0 and d["cores"] >= 1 and d["seconds_per_solve"] > 0
     assert "16^3x32" in d["sample"] and "1e-10" in d["sample"]
+
+
+def test_bench_defines_every_measurement():
+    """Every function the benchmark's main() calls is defined (a missing one would only show as a
+    NameError on the GPU machine)."""
+    import ast
+
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    tree = ast.parse(src)
+    defined = {n.name for n in tree.body if isinstance(n, ast.FunctionDef)}
+    main = next(n for n in tree.body if isinstance(n, ast.FunctionDef) and n.name == "main")
+    called = {c.func.id for c in ast.walk(main) if isinstance(c, ast.Call) and isinstance(c.func, ast.Name)}
+    defined |= {n.name for n in ast.walk(main) if isinstance(n, ast.FunctionDef)}  # closures inside main()
+    import builtins
+
+    missing = {f for f in called if f not in defined and not hasattr(builtins, f)}
+    assert not missing, missing
+    for f in ("cpu_baseline", "tsm_comparison", "copy_rate", "hop_rate", "dslash_sweep", "differentiation_measurement",
+              "batch_measurement", "dilution_study"):
+        assert f in defined, f
