@@ -212,3 +212,24 @@ def test_full_size_link_gradient_directional(dl, dev):
     an = np.sum((np.conj(grad) * dU).real)
     # central-difference error ~ h^2 F''' + tol |F| / h; both far below 1e-5 of |an| here
     assert abs(fd - an) < 1e-5 * abs(an), (fd, an)
+
+
+def test_full_size_dkappa_rounds_match_single_noise_calls(dl, dev):
+    """The differentiation workload in the launch configuration the benchmark times (24^3 x 48,
+    32 spin-colour-diluted noises = 384 right-hand sides, FP32 iterations with FP64 reliable updates
+    to 1e-10), which the library runs in two workspace rounds: sampled noises from either round equal
+    the same noise computed alone (the single-noise path is the one checked against the oracle and
+    against central differences)."""
+    w = synth.WORKLOADS["grad_24x24x24x48"]
+    dims, kappa = w["dims"], w["kappa"]
+    U = synth.gauge_field(dims, w["eps"], w["gauge_seed"])
+    G = dl.Gauge(dl.Lattice(dims, 1), U, precs=(dl.DL_F64, dl.DL_F32))
+    gam = [15, 0]
+    prm = dl.solve_params(prec=dl.DL_F32, tol=1e-10, maxiter=2000)
+    d, st = dl.loops_dkappa(G, kappa, dl.z2_sources(w["noise_seed"], 32, scheme=dl.DL_DIL_SPIN_COLOUR), gam, prm)
+    assert len(st) == 2 * 384 and all(s[0] == dl.DL_OK for s in st)
+    for n in (0, 17, 31):
+        d1, st1 = dl.loops_dkappa(G, kappa, dl.z2_sources(w["noise_seed"], 1, first_noise=n,
+                                                          scheme=dl.DL_DIL_SPIN_COLOUR), gam, prm)
+        assert all(s[0] == dl.DL_OK for s in st1)
+        assert rel(d[n], d1[0]) < 1e-7, (n, rel(d[n], d1[0]))
