@@ -1058,9 +1058,11 @@ void cgnr_batch(const Ctx &c, double kappa, int iters, SolveWork &w)
             dcall(c, P, 0, true, EPI_XPAY_DOT, w.tmpo.view(), w.v.view(), w.t.view(), w.p.view(), -k2, n, parts, act),
             c.s);
         scalar_launch(S_CG_ALPHA, sseg(nbd), SParams{}, c.s);
-        vec_launch(V_CG_XR, P, {vs({w.x64.view(), w.r.view(), w.p.view(), w.v.view()}, Vh, n, act, parts, st)}, c.s);
+        // r -= alpha q with |r|^2; beta; then x += alpha p and p = r + beta p in one pass (a right-hand
+        // side that finishes in this iteration is flagged 2, so it still takes its x update)
+        vec_launch(V_CG_XR, P, {vs({w.r.view(), w.v.view()}, Vh, n, act, parts, st)}, c.s);
         scalar_launch(S_CG_BETA, sseg(nb), SParams{}, c.s);
-        vec_launch(V_CG_P, P, {vs({w.p.view(), w.r.view()}, Vh, n, act, nullptr, st)}, c.s);
+        vec_launch(V_CG_P, P, {vs({w.p.view(), w.r.view(), w.x64.view()}, Vh, n, act, nullptr, st)}, c.s);
     }
     launch_dslash(
         dcall(c, P, 1, false, EPI_XPAY, w.x64.view(), w.xo.view(), w.bo.view(), NOF, kappa, n, nullptr, nullptr), c.s);

@@ -184,6 +184,10 @@ __device__ void cg_init(const SSeg &a, const SParams &p, int rhs)
 __device__ void cg_alpha(const SSeg &a, int rhs)
 {
     if (!a.act[rhs]) return;
+    if (a.act[rhs] == 2) {  // finished last iteration (its x update is done): now inactive
+        if (threadIdx.x == 0) a.act[rhs] = 0;
+        return;
+    }
     double pq = sum_parts(a.parts, rhs, a.nblk, 2, 0);
     if (threadIdx.x != 0) return;
     KState s = a.st[rhs];
@@ -207,7 +211,8 @@ __device__ void cg_beta(const SSeg &a, int rhs)
     s.beta[1] = 0;
     s.rr = rr;
     s.iters += 1;
-    if (s.iters >= s.maxiter || !(rr > 0)) a.act[rhs] = 0;
+    // finished: 2 keeps it live for this iteration's x update (V_CG_P)
+    if (s.iters >= s.maxiter || !(rr > 0)) a.act[rhs] = 2;
     a.st[rhs] = s;
 }
 
@@ -251,8 +256,8 @@ __device__ __forceinline__ void write_parts(double v[NP], double *red, double *p
 //   V_BICG_P  p = r + beta (p - omega v)                                        f: p, r, v
 //   V_BICG_S  r = r - alpha v                                                   f: r, v
 //   V_BICG_XR x += alpha p + omega s; r = s - omega t; parts (rhat, r), |r|^2   f: x, r(s), p, t, rhat
-//   V_CG_XR   x += alpha p; r -= alpha q; parts |r|^2                           f: x, r, p, q
-//   V_CG_P    p = r + beta p                                                    f: p, r
+//   V_CG_XR   r -= alpha q; parts |r|^2                                         f: r, q
+//   V_CG_P    x += alpha p; p = r + beta p                                      f: p, r, x
 //   V_ZERO    f0 = 0
 //   V_NORM2   parts |f0|^2
 //   V_DOT     parts (f0, f1)
@@ -312,29 +317,30 @@ __device__ __forceinline__ void vec_item(const VSeg &a, int item, double *red)
         double part[1] = {0};
         if (valid) {
             const R alpha = R(a.st[rhs].alpha[0]);
-            cx<R> xv[12], rv[12], pv[12], qv[12];
-            load_spinor<S, true>(a.f[0], Vh, rhs, cb, xv);
-            load_spinor<S, true>(a.f[1], Vh, rhs, cb, rv);
-            load_spinor<S, true>(a.f[2], Vh, rhs, cb, pv);
-            load_spinor<S, true>(a.f[3], Vh, rhs, cb, qv);
+            cx<R> rv[12], qv[12];
+            load_spinor<S, true>(a.f[0], Vh, rhs, cb, rv);
+            load_spinor<S, true>(a.f[1], Vh, rhs, cb, qv);
 #pragma unroll
             for (int e = 0; e < 12; ++e) {
-                xv[e] = xv[e] + alpha * pv[e];
                 rv[e] = rv[e] - alpha * qv[e];
                 part[0] += (double)rv[e].re * rv[e].re + (double)rv[e].im * rv[e].im;
             }
-            store_spinor<S, true>(a.f[0], Vh, rhs, cb, xv);
-            store_spinor<S, true>(a.f[1], Vh, rhs, cb, rv);
+            store_spinor<S, true>(a.f[0], Vh, rhs, cb, rv);
         }
         write_parts<1>(part, red, a.parts, rhs, nb, blk);
     } else if constexpr (OP == V_CG_P) {
         if (!valid) return;
-        const R beta = R(a.st[rhs].beta[0]);
-        cx<R> pv[12], rv[12];
+        const R alpha = R(a.st[rhs].alpha[0]), beta = R(a.st[rhs].beta[0]);
+        cx<R> pv[12], rv[12], xv[12];
         load_spinor<S, true>(a.f[0], Vh, rhs, cb, pv);
         load_spinor<S, true>(a.f[1], Vh, rhs, cb, rv);
+        load_spinor<S, true>(a.f[2], Vh, rhs, cb, xv);
 #pragma unroll
-        for (int e = 0; e < 12; ++e) pv[e] = rv[e] + beta * pv[e];
+        for (int e = 0; e < 12; ++e) {
+            xv[e] = xv[e] + alpha * pv[e];
+            pv[e] = rv[e] + beta * pv[e];
+        }
+        store_spinor<S, true>(a.f[2], Vh, rhs, cb, xv);
         store_spinor<S, true>(a.f[0], Vh, rhs, cb, pv);
     } else if constexpr (OP == V_ZERO) {
         if (!valid) return;
@@ -529,7 +535,7 @@ void scalar_launch(int op, const std::vector<SSeg> &segs, const SParams &p, hipS
 
 void vec_launch(int op, int prec, const std::vector<VSeg> &segs, hipStream_t s)
 {
-    static const int nvec[] = {4, 3, 7, 6, 3, 1, 1, 2};
+    static const int nvec[] = {4, 3, 7, 3, 5, 1, 1, 2};
     ProfScope ps(PROF_BLAS, vec_bytes(prec, segs, nvec[op]), s);
     const std::vector<VSeg> sg =
         counted_segs(segs, ps, s, [&](int64_t Vh) { return nvec[op] * field_rhs_bytes(prec, Vh); });
