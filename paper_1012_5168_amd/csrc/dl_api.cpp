@@ -1097,7 +1097,12 @@ int batch_size(size_t per_rhs, int64_t total, int quantum)
     int64_t b = (int64_t)(workspace_limit() / std::max<size_t>(per_rhs, 1));
     b = std::min<int64_t>(b, 65535);
     b = std::max<int64_t>(b / quantum * quantum, quantum);
-    return (int)std::min<int64_t>(b, total);
+    // as many rounds as the limit needs, of equal size: one workspace (and one
+    // cached buffer) then serves every round, instead of a full round and a
+    // smaller remainder that the cache cannot serve from the first's buffer
+    const int64_t rounds = (total + b - 1) / b;
+    const int64_t even = ((total + rounds - 1) / rounds + quantum - 1) / quantum * quantum;
+    return (int)std::min<int64_t>(std::min<int64_t>(b, even), total);
 }
 
 void fill_stats(const SolveWork &w, const std::vector<double> &res2, dl_solve_stats *out, hipStream_t s,
@@ -1659,7 +1664,8 @@ extern "C" int dl_batch_loops(int32_t n_lat, const dl_gauge *gauges, const doubl
                              source_classes(&srcs[l]);
             max_noise = std::max(max_noise, srcs[l].n_noise);
         }
-        const int k = (int)std::max<int64_t>(1, std::min<int64_t>(max_noise, workspace_limit() / per_noise_all));
+        const int kmax = (int)std::max<int64_t>(1, std::min<int64_t>(max_noise, workspace_limit() / per_noise_all));
+        const int k = (max_noise + (max_noise + kmax - 1) / kmax - 1) / ((max_noise + kmax - 1) / kmax);  // equal rounds
         std::vector<double> gtab = gamma_table();
         DevBuf dgam(gtab.size() * sizeof(double)), dgidx(sizeof(int) * n_gamma);
         DL_HIP(hipMemcpyAsync(dgam.p, gtab.data(), dgam.bytes, hipMemcpyHostToDevice, s));
