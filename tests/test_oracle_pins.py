@@ -15,7 +15,9 @@ that does not share its code:
 * Solver and contraction: dense LU (numpy.linalg.inv) on 2^4 and 4^3 x 4,
   point-source loops against the dense diagonal, the real / imaginary classes
   of Tr[Gamma M^-1(x,x)], gauge invariance of exact loops.
-* Noise and dilution: every entry in {(+-1 +-i)/sqrt 2}, phase balance,
+* Noise and dilution: the counter form of SplitMix64 against the generator
+  stepped sequentially and against the published known-answer outputs for
+  seed 0 (tests/golden/); every entry in {(+-1 +-i)/sqrt 2}, phase balance,
   unbiasedness and the closed-form variance sum_{i!=j} |A_ij|^2 of the complex
   Z2 trace estimator, dilution classes against coordinates computed here; for
   every valid scheme the diluted pieces partition the noise and each piece is
@@ -37,8 +39,9 @@ that does not share its code:
 * Disconnected correlator (Eq. 2): identical per-noise estimates against the
   circular cross-correlation computed with numpy's FFT (convolution theorem);
   unbiasedness over distinct noise pairs when the two loops of one noise are
-  correlated (z-test), with the same-noise estimator shown to be biased on the
-  same data; the B <-> A swap symmetry D^BA(dt) = D^AB(T - dt).
+  correlated (z-test), with the same-noise estimator's expectation z-tested
+  against its closed-form bias -c E[xi^2] / (N L^3) at dt = 0, ten standard
+  errors from zero on the same data; the B <-> A swap symmetry D^BA(dt) = D^AB(T - dt).
 * eta' combination and ratio fit (Eqs. 3-4): noise-free correlators built
   here from chosen (A, B, m_eta', m_pi) are fitted back exactly, and a wrong
   sign of B or a dropped backward-propagating term in the model would not
@@ -48,12 +51,15 @@ that does not share its code:
   (the closed form of the jackknife for a mean) and zero errors for B and m.
 """
 import itertools
+import os
 
 import numpy as np
 import pytest
 
 import oracle
 import synth
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
 
@@ -348,13 +354,37 @@ def test_z2_entries_and_balance():
     assert abs(np.mean(r[1:] * r[:-1])) < 4 / np.sqrt(n)
 
 
+def _splitmix64_stream(seed, n):
+    """The generator as published (Steele, Lea and Flood 2014): the state advances by the golden
+    gamma each step and every output is the mix of the new state; stepped here one output at a
+    time."""
+    m = (1 << 64) - 1
+    state, out = seed & m, []
+    for _ in range(n):
+        state = (state + 0x9E3779B97F4A7C15) & m
+        z = state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m
+        out.append(z ^ (z >> 31))
+    return out
+
+
 def test_splitmix64_counter_equals_sequential_stream():
-    """The counter form (state = seed + (c+1)*gamma) agrees with stepping the generator c+1 times."""
-    seed = 0x1234_5678_9ABC_DEF0
-    outs = [oracle.splitmix64(seed, c) for c in range(64)]
-    assert len(set(outs)) == 64
-    # bits 0 and 1 are balanced over a long counter range
-    b = np.array([oracle.splitmix64(seed, c) & 3 for c in range(4000)])
+    """The counter form (output c computed directly from seed + (c+1) gamma) equals output c of the
+    sequentially stepped generator, for 64 consecutive outputs of several seeds and for a far
+    counter reached by stepping, and the stream of seed 0 starts with the published outputs of the
+    reference generator (tests/golden/splitmix64_seed0.txt)."""
+    for seed in (0, 1, 2000, 0x1234_5678_9ABC_DEF0, (1 << 64) - 1):
+        seq = _splitmix64_stream(seed, 64)
+        assert [oracle.splitmix64(seed, c) for c in range(64)] == seq, seed
+    seq = _splitmix64_stream(2001, 5000)
+    assert oracle.splitmix64(2001, 4999) == seq[4999]
+    with open(os.path.join(GOLDEN, "splitmix64_seed0.txt")) as f:
+        known = [int(tok, 16) for line in f if not line.startswith("#") for tok in line.split()]
+    assert len(known) == 4
+    assert [oracle.splitmix64(0, c) for c in range(4)] == known
+    # bits 0 and 1 (the two signs of a complex Z2 entry) are balanced over a long counter range
+    b = np.array([oracle.splitmix64(0x1234_5678_9ABC_DEF0, c) & 3 for c in range(4000)])
     cnt = np.bincount(b, minlength=4)
     assert np.all(np.abs(cnt - 1000) < 4 * np.sqrt(750))
 
@@ -541,17 +571,21 @@ def test_correlator_identical_estimates_against_fft():
 
 def test_correlator_unbiased_over_distinct_noise_pairs():
     """Per-noise loops L_A^n = mu_A + xi_n and L_B^n = mu_B + c xi_n share their fluctuation xi_n
-    (real Gaussian, so E[xi(t) xi(t)] != 0), as two loops from the same source do.  The estimate
-    over n != m has expectation -1/(L^3 T) sum_t mu_B(t) mu_A(t+dt); including n == m adds
-    c E[xi(t) xi(t+dt)] / N, which the same data must show (so the test can tell the two apart)."""
+    (real Gaussian of variance s2 = 0.49, so E[xi(t) xi(t)] != 0), as two loops from the same source
+    do.  The estimate over n != m has expectation -1/(L^3 T) sum_t mu_B(t) mu_A(t+dt).  Including
+    n == m (all N^2 ordered pairs) adds c E[Xi(t) Xi(t+dt)] with Xi = sum_n xi_n, i.e. c N s2 delta_{dt,0}
+    per timeslice, so its expectation is off by the closed form -c s2 / (N L^3) at dt = 0 and exact
+    elsewhere.  Both expectations are z-tested, and the sample is large enough that the closed-form
+    bias is ten standard errors of the same-noise mean away from zero (the contrast that tells the
+    two estimators apart)."""
     rng = np.random.default_rng(72)
-    T, L3, N, reps = 4, 8, 5, 1500
+    T, L3, N, reps, s2 = 4, 8, 5, 4000, 0.49
     mu_a = rng.normal(size=T) + 1j * rng.normal(size=T)
     mu_b = rng.normal(size=T) + 1j * rng.normal(size=T)
     c = 0.8 + 0.3j
     est, biased = [], []
     for _ in range(reps):
-        xi = rng.normal(size=(N, T)) * 0.7
+        xi = rng.normal(size=(N, T)) * np.sqrt(s2)
         la, lb = mu_a + xi, mu_b + c * xi
         est.append(oracle.disconnected_correlator(lb, la, L3))
         # all ordered pairs including n == m, written with numpy for the contrast
@@ -559,13 +593,22 @@ def test_correlator_unbiased_over_distinct_noise_pairs():
         biased.append(np.array([-np.sum(sb * np.roll(sa, -dt)) / N ** 2 / (L3 * T) for dt in range(T)]))
     est, biased = np.array(est), np.array(biased)
     ref = np.array([-np.sum(mu_b * np.roll(mu_a, -dt)) / (L3 * T) for dt in range(T)])
-    se = est.std(axis=0, ddof=1) / np.sqrt(reps)
-    for part in (np.real, np.imag):
-        z = np.abs(part(est.mean(axis=0) - ref)) / part(se + 1j * se)
-        assert np.all(z < 4.5), z
-    # the same-noise estimator is off by -c 0.49 / (N L3) at dt = 0: many standard errors away
-    zb = np.abs(biased.mean(axis=0)[0] - ref[0]) / (np.abs(biased.std(axis=0, ddof=1)[0]) / np.sqrt(reps))
-    assert zb > 6, zb
+    bias = np.zeros(T, dtype=np.complex128)
+    bias[0] = -c * s2 / (N * L3)
+
+    def z(sample, expect):
+        se_re = sample.real.std(axis=0, ddof=1) / np.sqrt(reps)
+        se_im = sample.imag.std(axis=0, ddof=1) / np.sqrt(reps)
+        d = sample.mean(axis=0) - expect
+        return np.concatenate([np.abs(d.real) / se_re, np.abs(d.imag) / se_im])
+
+    assert np.all(z(est, ref) < 4.5), z(est, ref)
+    assert np.all(z(biased, ref + bias) < 4.5), z(biased, ref + bias)
+    se0 = np.abs(biased.std(axis=0, ddof=1)[0]) / np.sqrt(reps)
+    assert abs(bias[0]) / se0 > 10, abs(bias[0]) / se0
+    # and the measured offset of the same-noise estimator shows it too
+    zb = np.abs(biased.mean(axis=0)[0] - ref[0]) / se0
+    assert zb > 10, zb
 
 
 def test_correlator_swap_symmetry():
