@@ -125,27 +125,50 @@ void dl_lattice_destroy(dl_lattice lat);
 int64_t dl_lattice_volume(dl_lattice lat);
 
 /*
- * Upload a gauge field.  links: host canonical complex128 [4][V][3][3] of
- * special-unitary matrices (the third row is rebuilt from the first two when
- * recon = 12).  prec_mask: bit (1 << p) for each dl_prec p to keep resident
- * on the device.  recon: 12 (store two rows, rebuild the third as the
- * conjugated cross product) or 18 (store all three).  The time-boundary sign
- * is never folded into the stored links.  The handle keeps its own reference
- * to the lattice description; the lattice handle may be destroyed after.
+ * Upload a gauge field: the SU(3) link variables U_mu(x) of the N_f = 2
+ * Wilson-Dirac operator the paper inverts (Section 2: Wilson fermions on a
+ * 16^3 x 32 ensemble; here any even lattice).  links: host canonical
+ * complex128 [4][V][3][3] of special-unitary matrices (the third row is
+ * rebuilt from the first two when recon = 12).  prec_mask: bit (1 << p) for
+ * each dl_prec p to keep resident on the device.  recon: 12 (store two rows,
+ * rebuild the third as the conjugated cross product) or 18 (store all three;
+ * the only exact choice for links that are not special-unitary, e.g. when
+ * differentiating with respect to unconstrained matrices).  The
+ * time-boundary sign is never folded into the stored links (a negated
+ * 12-parameter link would rebuild the wrong third row).  The handle keeps its
+ * own copy of the lattice description; the lattice handle may be destroyed
+ * after.  The caller's buffer is not referenced after the call returns.
  * Errors: DL_EINVAL (null pointers, empty mask, recon not 12 or 18),
  * DL_ENOMEM, DL_EHIP.
  */
 int dl_gauge_create(dl_lattice lat, const double *links, uint32_t prec_mask, int32_t recon, void *stream,
                     dl_gauge *out);
+
+/*
+ * As dl_gauge_create, with the links in device memory (canonical complex128
+ * [4][V][3][3], e.g. a torch tensor's data_ptr()): the reordering into the
+ * library's layout runs on the device, ordered on `stream`; no host copy of
+ * the field is made.  The caller's buffer is not referenced after the call
+ * returns.  Errors as dl_gauge_create.
+ */
+int dl_gauge_create_device(dl_lattice lat, const void *links, uint32_t prec_mask, int32_t recon, void *stream,
+                           dl_gauge *out);
 void dl_gauge_destroy(dl_gauge g);
 
 /*
- * out = op(in) for nrhs fields.  in, out: device canonical complex128
- * [nrhs][V][4][3]; they must not overlap.  prec: storage precision of the
- * links and fields the operator runs in (must be resident in the gauge
- * handle); results are converted back to complex128.  kappa is ignored for
- * DL_OP_DHOP / DL_OP_DHOPDAG.  Errors: DL_EINVAL (null pointer, nrhs < 1,
- * unknown op, precision not resident), DL_ENOMEM, DL_EHIP.
+ * out = op(in) for nrhs fields: the Wilson-Dirac matrix M = 1 - kappa D_hop
+ * whose inverse the method needs (Section 2), its adjoint, the hopping term
+ * alone, or the even-site Schur complement the even-odd preconditioned
+ * solver iterates on (M = [[1, -k D_eo], [-k D_oe, 1]] in even-odd blocks,
+ * so M^-1 restricted to even sites is the inverse of 1 - k^2 D_eo D_oe).
+ * in, out: device canonical complex128 [nrhs][V][4][3], owned by the
+ * caller; they must not overlap.  prec: storage precision of the links and
+ * fields the operator runs in (must be resident in the gauge handle; the
+ * reduced precisions of the truncated solver method, Section 2); results are
+ * converted back to complex128.  kappa is ignored for DL_OP_DHOP /
+ * DL_OP_DHOPDAG.  nrhs in [1, 65535].  Errors: DL_EINVAL (null pointer, nrhs
+ * outside its range, unknown op, precision not resident, in == out),
+ * DL_ENOMEM, DL_EHIP; out is undefined after an error other than DL_EINVAL.
  */
 int dl_apply(dl_gauge g, double kappa, int32_t op, int32_t prec, const void *in, void *out, int64_t nrhs,
              void *stream);
@@ -162,7 +185,10 @@ typedef struct {
                             (0 -> 0.01) */
     int32_t poll;        /* iterations between host convergence checks (0 -> automatic) */
     int32_t use_graph;   /* 1: capture `poll` BiCGStab iterations once as a hipGraph and replay it
-                            (the first chunk runs eagerly and tunes the launch shapes) */
+                            (the first chunk runs eagerly and tunes the launch shapes).  A failure
+                            during the capture ends it before the call returns, so the stream is
+                            usable again.  For tests of that path, the environment variable
+                            DL_FAULT_INJECT=capture makes every capture fail after it has begun. */
 } dl_solve_params;
 
 /* Per right-hand side results of a solve. */
@@ -171,15 +197,30 @@ typedef struct {
     int32_t iters;            /* Krylov iterations */
     int32_t reliable_updates; /* FP64 residual replacements */
     int32_t pad;
-    double true_rel_residual; /* FP64 |b - M x| / |b| of the returned solution */
+    double true_rel_residual; /* FP64 |b - M x| / |b| of the returned solution (0 where not computed) */
+    double seconds;           /* this right-hand side's share of the wall time of its batch (the
+                                 batch's time divided by its right-hand sides) */
+    double bytes;             /* algorithmic bytes of its field operands: every operand of every kernel
+                                 its solve ran, moved once (per iteration 25 half fields for BiCGStab,
+                                 19 for CGNR, in the iteration precision; per reliable update 8 FP64
+                                 and 3 iteration-precision half fields; set-up and reconstruction); the
+                                 links, shared by the batch, are not counted */
 } dl_solve_stats;
 
 /*
- * Solve M x = b (even-odd preconditioned: the Schur system on even sites,
- * then x_o = b_o + kappa D_oe x_e) for nrhs right-hand sides.  b, x: device
- * canonical complex128 [nrhs][V][4][3], not overlapping.  stats: host
- * [nrhs] or NULL.  Returns DL_ENOCONV if any tolerance-driven solve did not
- * converge within maxiter (x holds the last iterate).
+ * Solve M x = b for nrhs right-hand sides: the inversions the method consists
+ * of (Section 2; the paper uses mixed-precision CG/BiCGStab, here even-odd
+ * preconditioned BiCGStab with FP64 reliable updates, or the truncated CGNR
+ * of the truncated solver method's low-precision solves).  Even-odd: the
+ * Schur system (1 - k^2 D_eo D_oe) x_e = b_e + k D_eo b_o on even sites, then
+ * x_o = b_o + k D_oe x_e.  A tolerance-driven solve has converged when the
+ * FP64 true residual |b - M x| / |b| of the full system is <= tol.  b, x:
+ * device canonical complex128 [nrhs][V][4][3], owned by the caller, not
+ * overlapping.  stats: host [nrhs] or NULL.  Right-hand sides run in batches
+ * that fit the workspace limit (DL_WORKSPACE_GB, default 160).  Returns
+ * DL_ENOCONV if any tolerance-driven solve did not converge within maxiter
+ * (x holds the last iterate, stats say which), DL_ENAN for a non-finite
+ * value, DL_EINVAL for invalid arguments (before any device work).
  */
 int dl_solve(dl_gauge g, double kappa, const dl_solve_params *params, const void *b, void *x, int64_t nrhs,
              dl_solve_stats *stats, void *stream);
@@ -217,14 +258,31 @@ typedef struct {
 } dl_tsm;
 
 /*
+ * The truncated solver method's estimate and its variance (Section 2), in
+ * FP64 on the host:
+ *     est[g][t] = mean_{j in LP set} L^LP_j + mean_{j in HP set} (L^HP_j - L^LP_j),
+ *     var[g][t] = s2(L^LP)/n_lp + s2(L^HP - L^LP)/n_hp,
+ * s2 the unbiased sample variance of complex values (sum of |z - mean|^2 over
+ * n - 1), i.e. the variance of est when the noises are independent.
+ * lp_set_lp: host [n_lp][n_gamma][T][2] (the LP set's low-precision loops);
+ * hp_set_hp, hp_set_lp: host [n_hp][n_gamma][T][2] (the HP set's high- and
+ * low-precision loops) -- the three blocks of the dl_loops_tsm output, or any
+ * resampling of them.  est: host [n_gamma][T][2]; var: host [n_gamma][T] or
+ * NULL.  Errors: DL_EINVAL (null pointer, n_lp or n_hp < 1, or < 2 when var
+ * is requested, n_gamma outside [1, 16], T outside [1, 65535]).
+ */
+int dl_tsm_combine(const double *lp_set_lp, int32_t n_lp, const double *hp_set_hp, const double *hp_set_lp,
+                   int32_t n_hp, int32_t n_gamma, int32_t T, double *est, double *var);
+
+/*
  * Truncated solver method (Section 2): low-precision solves on all
  * n_lp + n_hp noises of src (src->n_noise must equal n_lp + n_hp) and
  * high-precision solves on the n_hp correction noises.  loops: host double
  * [n_lp + 2 n_hp][n_gamma][T][2] holding, per noise as in dl_loops, first the
  * LP-set low-precision loops, then the HP-set high-precision loops, then the
  * HP-set low-precision loops.  The estimate is mean(LP set, low) +
- * mean(HP set, high - low); it and its variance are formed by the caller in
- * FP64.  stats: host [(n_lp + n_hp) * classes + n_hp * classes] (the
+ * mean(HP set, high - low), formed with its variance by dl_tsm_combine.
+ * stats: host [(n_lp + n_hp) * classes + n_hp * classes] (the
  * low-precision solves, then the high-precision ones) or NULL.
  */
 int dl_loops_tsm(dl_gauge g, double kappa, const dl_sources *src, const dl_tsm *tsm, const int32_t *gammas,
@@ -248,16 +306,17 @@ int dl_loops_dkappa(dl_gauge g, double kappa, const dl_sources *src, const dl_so
  * a = M^-dagger (sum_g w Gamma_g^+ P_t eta) = gamma5 M^-1 gamma5 (...), the
  * variation is dF = Re kappa sum a^+ dD s (two solves per right-hand side,
  * tolerance-driven BiCGStab only).  w: host double [n_noise][n_gamma][T][2]
- * (the cotangent of the loops).  grad: host double [4][V][3][3][2]
- * (overwritten).  loops: host [n_noise][n_gamma][T][2] or NULL (the forward
- * loops, as dl_loops).  dloops: host [n_noise][n_gamma][T][2] or NULL (the
- * kappa derivative, as dl_loops_dkappa, at the cost of a third solve).
- * stats: host [2 or 3][n_noise * classes] (forward, adjoint, kappa solves) or
- * NULL.
+ * (the cotangent of the loops).  grad: host or device double
+ * [4][V][3][3][2] (overwritten).  loops: host [n_noise][n_gamma][T][2] or
+ * NULL (the forward loops, as dl_loops).  dloops: host
+ * [n_noise][n_gamma][T][2] or NULL (the kappa derivative, as
+ * dl_loops_dkappa, at the cost of a third solve).  dF_dkappa: host double or
+ * NULL: dF/dkappa = Re sum conj(w) dloops (also a third solve).  stats: host
+ * [2 or 3][n_noise * classes] (forward, adjoint, kappa solves) or NULL.
  */
 int dl_loops_link_grad(dl_gauge g, double kappa, const dl_sources *src, const dl_solve_params *params,
                        const int32_t *gammas, int32_t n_gamma, const double *w, double *grad, double *loops,
-                       double *dloops, dl_solve_stats *stats, void *stream);
+                       double *dloops, double *dF_dkappa, dl_solve_stats *stats, void *stream);
 
 /*
  * Loop estimates on up to 4 lattices of different shapes at once (each with
@@ -357,14 +416,21 @@ int dl_eta_prime_fit(const double *d, const double *c_pi, int32_t ncfg, int32_t 
  * Device memory cache.  The library keeps the device buffers its calls
  * release (workspaces, staging) and serves later calls of the same shape from
  * them instead of allocating again; mapping multi-GB workspaces anew would
- * otherwise cost seconds per call.  A buffer enters the cache only after the
- * device has finished its queued work.  The environment variable DL_CACHE_GB
- * (read once) caps the cached bytes (default 256; 0 disables caching); an
- * allocation that fails releases the cache and retries once.
- * dl_cache_release frees every cached buffer (it synchronises the device) and
- * returns DL_OK.
+ * otherwise cost seconds per call.  A released buffer carries an event
+ * recorded on the releasing call's stream, and a later call that takes it
+ * waits for that event first.  The cached bytes are capped: the environment
+ * variable DL_CACHE_GB (read at the first release; default 64, 0 disables
+ * caching) or dl_cache_set_limit.  An allocation that fails releases the
+ * cache and retries once.  Cached memory is not available to other
+ * allocators (e.g. torch's) until it is released.
+ * dl_cache_release frees every cached buffer (after waiting for its last
+ * user) and returns DL_OK.  dl_cache_set_limit sets the cap in bytes (0 turns
+ * caching off) and frees cached buffers beyond it.  dl_cache_bytes returns
+ * the bytes held.
  */
 int dl_cache_release(void);
+int dl_cache_set_limit(uint64_t bytes);
+uint64_t dl_cache_bytes(void);
 
 /*
  * Kernel profiling on the library's streams.  dl_profile_enable(1) resets the

@@ -66,6 +66,8 @@ class dl_solve_stats(ctypes.Structure):
         ("reliable_updates", ctypes.c_int32),
         ("pad", ctypes.c_int32),
         ("true_rel_residual", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+        ("bytes", ctypes.c_double),
     ]
 
 
@@ -97,6 +99,7 @@ _SIGNATURES = {
     "dl_lattice_destroy": (None, [_P]),
     "dl_lattice_volume": (ctypes.c_int64, [_P]),
     "dl_gauge_create": (ctypes.c_int, [_P, _P, ctypes.c_uint32, ctypes.c_int32, _P, ctypes.POINTER(_P)]),
+    "dl_gauge_create_device": (ctypes.c_int, [_P, _P, ctypes.c_uint32, ctypes.c_int32, _P, ctypes.POINTER(_P)]),
     "dl_gauge_destroy": (None, [_P]),
     "dl_apply": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int64, _P]),
     "dl_solve": (ctypes.c_int, [_P, ctypes.c_double, ctypes.POINTER(dl_solve_params), _P, _P, ctypes.c_int64,
@@ -114,7 +117,9 @@ _SIGNATURES = {
                                        ctypes.POINTER(dl_solve_stats), _P]),
     "dl_loops_link_grad": (ctypes.c_int, [_P, ctypes.c_double, ctypes.POINTER(dl_sources),
                                           ctypes.POINTER(dl_solve_params), _P, ctypes.c_int32, _P, _P, _P, _P,
-                                          ctypes.POINTER(dl_solve_stats), _P]),
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(dl_solve_stats), _P]),
+    "dl_tsm_combine": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                      _P, _P]),
     "dl_batch_loops": (ctypes.c_int, [ctypes.c_int32, _P, _P, _P, ctypes.POINTER(dl_solve_params), _P,
                                       ctypes.c_int32, _P, _P, _P]),
     "dl_sources_count": (ctypes.c_int64, [_P, ctypes.POINTER(dl_sources)]),
@@ -124,6 +129,8 @@ _SIGNATURES = {
     "dl_eta_prime_fit": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                         ctypes.c_int32, _P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
     "dl_cache_release": (ctypes.c_int, []),
+    "dl_cache_set_limit": (ctypes.c_int, [ctypes.c_uint64]),
+    "dl_cache_bytes": (ctypes.c_uint64, []),
     "dl_profile_enable": (ctypes.c_int, [ctypes.c_int32]),
     "dl_profile_config": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "dl_profile_read": (ctypes.c_int64, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
@@ -172,6 +179,19 @@ def _dptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _as_complex(buf):
+    """A float64 [..., 2] (re, im) buffer read as complex128 [...] in place (no copy, no arithmetic)."""
+    return buf.view(np.complex128)[..., 0]
+
+
+def _as_pairs(z, shape=None):
+    """complex values as a contiguous float64 [..., 2] (re, im) array (a reinterpretation of the bytes)."""
+    z = np.ascontiguousarray(z, dtype=np.complex128)
+    if shape is not None:
+        z = np.ascontiguousarray(np.broadcast_to(z, shape))
+    return z.view(np.float64).reshape(z.shape + (2,))
+
+
 # ------------------------------------------------------------------ same-name wrappers
 
 
@@ -199,6 +219,14 @@ def dl_gauge_create(lat, links: np.ndarray, prec_mask: int, recon: int = 12, str
     h = _P()
     _check(load().dl_gauge_create(lat, links.ctypes.data_as(_P), int(prec_mask), int(recon), _stream(stream),
                                   ctypes.byref(h)))
+    return h
+
+
+def dl_gauge_create_device(lat, links, prec_mask: int, recon: int = 12, stream=None):
+    """links: a contiguous complex128 device tensor [4][V][3][3]."""
+    h = _P()
+    _check(load().dl_gauge_create_device(lat, _dptr(links), int(prec_mask), int(recon), _stream(stream),
+                                         ctypes.byref(h)))
     return h
 
 
@@ -257,17 +285,26 @@ def dl_loops_dkappa(gauge, kappa, sources, params, gammas, dloops_out: np.ndarra
     return rc
 
 
-def dl_loops_link_grad(gauge, kappa, sources, params, gammas, w: np.ndarray, grad_out: np.ndarray,
-                       loops_out: np.ndarray | None = None, dloops_out: np.ndarray | None = None, stats=None,
-                       stream=None):
+def dl_loops_link_grad(gauge, kappa, sources, params, gammas, w: np.ndarray, grad_out,
+                       loops_out: np.ndarray | None = None, dloops_out: np.ndarray | None = None,
+                       dF_dkappa=None, stats=None, stream=None):
+    """grad_out: a host float64 array [4][V][3][3][2] or a device tensor of the same bytes."""
     g = np.ascontiguousarray(np.asarray(gammas, dtype=np.int32))
     w = np.ascontiguousarray(w, dtype=np.float64)
     ptr = lambda a: None if a is None else a.ctypes.data_as(_P)  # noqa: E731
+    gp = grad_out.ctypes.data_as(_P) if isinstance(grad_out, np.ndarray) else _dptr(grad_out)
     rc = load().dl_loops_link_grad(gauge, float(kappa), ctypes.byref(sources), ctypes.byref(params),
-                                   g.ctypes.data_as(_P), len(g), w.ctypes.data_as(_P), grad_out.ctypes.data_as(_P),
-                                   ptr(loops_out), ptr(dloops_out), stats, _stream(stream))
+                                   g.ctypes.data_as(_P), len(g), w.ctypes.data_as(_P), gp, ptr(loops_out),
+                                   ptr(dloops_out), None if dF_dkappa is None else ctypes.byref(dF_dkappa), stats,
+                                   _stream(stream))
     _check(rc, allow=(DL_ENOCONV,))
     return rc
+
+
+def dl_tsm_combine(lp_set_lp, n_lp, hp_set_hp, hp_set_lp, n_hp, n_gamma, T, est, var=None):
+    _check(load().dl_tsm_combine(lp_set_lp.ctypes.data_as(_P), int(n_lp), hp_set_hp.ctypes.data_as(_P),
+                                 hp_set_lp.ctypes.data_as(_P), int(n_hp), int(n_gamma), int(T),
+                                 est.ctypes.data_as(_P), None if var is None else var.ctypes.data_as(_P)))
 
 
 def dl_batch_loops(gauges, kappas, sources, params, gammas, loops_out, stats=None, stream=None):
@@ -307,14 +344,13 @@ def dl_disconnected_correlator(loops_b, loops_a, n_noise, T, spatial_volume, cor
 def disconnected_correlator(loops_b, loops_a, spatial_volume, stream=None):
     """D(dt) of two per-noise loop sets (complex [n_noise][T] each), over distinct noise pairs;
     returns complex [T]."""
-    lb = np.ascontiguousarray(np.stack([np.real(loops_b), np.imag(loops_b)], axis=-1), dtype=np.float64)
-    la = np.ascontiguousarray(np.stack([np.real(loops_a), np.imag(loops_a)], axis=-1), dtype=np.float64)
+    lb, la = _as_pairs(loops_b), _as_pairs(loops_a)
     if lb.shape != la.shape or lb.ndim != 3:
         raise ValueError("loops_b and loops_a must both be [n_noise][T] complex")
     n, T = lb.shape[0], lb.shape[1]
     out = np.zeros((T, 2), dtype=np.float64)
     dl_disconnected_correlator(lb, la, n, T, spatial_volume, out, stream)
-    return out[:, 0] + 1j * out[:, 1]
+    return _as_complex(out)
 
 
 def dl_eta_prime_fit(d, c_pi, ncfg, T, m_pi, tmin, tmax, c_eta, params, errors):
@@ -368,7 +404,7 @@ def solve_params(solver=DL_BICGSTAB, prec=DL_F64, tol=1e-10, maxiter=1000, fixed
 
 
 def z2_sources(seed, n_noise, first_noise=0, scheme=0):
-    return dl_sources(DL_SRC_Z2, int(scheme), int(seed) & (2**64 - 1), int(first_noise), int(n_noise), 0)
+    return dl_sources(DL_SRC_Z2, int(scheme), int(seed) & 0xFFFFFFFFFFFFFFFF, int(first_noise), int(n_noise), 0)
 
 
 def point_sources(site):
@@ -378,8 +414,8 @@ def point_sources(site):
 class Lattice:
     def __init__(self, dims, t_antiperiodic=True):
         self.dims = tuple(int(d) for d in dims)
-        self.V = int(np.prod(self.dims))
         self.h = dl_lattice_create(self.dims, 1 if t_antiperiodic else 0)
+        self.V = int(load().dl_lattice_volume(self.h))
 
     def __del__(self):
         if getattr(self, "h", None) is not None and _lib is not None:
@@ -388,12 +424,20 @@ class Lattice:
 
 
 class Gauge:
-    def __init__(self, lattice: Lattice, links: np.ndarray, precs=(DL_F64,), recon=12, stream=None):
+    """A gauge field resident on the device.  links: a host complex128 array [4][V][3][3], or a
+    contiguous complex128 torch tensor of that shape on the GPU (uploaded without a host copy)."""
+
+    def __init__(self, lattice: Lattice, links, precs=(DL_F64,), recon=12, stream=None):
         self.lattice = lattice
         mask = 0
         for p in precs:
             mask |= 1 << int(p)
-        self.h = dl_gauge_create(lattice.h, links, mask, recon, stream)
+        if isinstance(links, np.ndarray):
+            self.h = dl_gauge_create(lattice.h, links, mask, recon, stream)
+        else:
+            if not links.is_contiguous():
+                raise ValueError("device links must be a contiguous complex128 tensor [4][V][3][3]")
+            self.h = dl_gauge_create_device(lattice.h, links, mask, recon, stream)
 
     def __del__(self):
         if getattr(self, "h", None) is not None and _lib is not None:
@@ -446,7 +490,7 @@ def loops_smeared(gauge: Gauge, kappa: float, sources: dl_sources, alpha: float,
     buf = np.zeros((int(sources.n_noise), len(gammas), T, 2), dtype=np.float64)
     st = (dl_solve_stats * dl_sources_count(gauge.lattice.h, sources))()
     dl_loops_smeared(gauge.h, kappa, sources, alpha, iters, params, gammas, buf, st, stream)
-    return buf[..., 0] + 1j * buf[..., 1], _stats_list(st)
+    return _as_complex(buf), _stats_list(st)
 
 
 def loops(gauge: Gauge, kappa: float, sources: dl_sources, gammas, params=None, stream=None):
@@ -458,8 +502,7 @@ def loops(gauge: Gauge, kappa: float, sources: dl_sources, gammas, params=None, 
     nrhs = dl_sources_count(gauge.lattice.h, sources)
     st = (dl_solve_stats * nrhs)()
     dl_loops(gauge.h, kappa, sources, params, gammas, buf, st, stream)
-    stats = [(s.status, s.iters, s.reliable_updates, s.true_rel_residual) for s in st]
-    return buf[..., 0] + 1j * buf[..., 1], stats
+    return _as_complex(buf), _stats_list(st)
 
 
 def _stats_list(st):
@@ -475,17 +518,21 @@ def loops_tsm(gauge: Gauge, kappa: float, sources: dl_sources, n_lp: int, n_hp: 
     ncls = dl_sources_count(gauge.lattice.h, sources) // int(sources.n_noise)
     st = (dl_solve_stats * ((n_lp + 2 * n_hp) * ncls))()
     dl_loops_tsm(gauge.h, kappa, sources, dl_tsm(n_lp, n_hp, lp_params, hp_params), gammas, buf, st, stream)
-    z = buf[..., 0] + 1j * buf[..., 1]
+    z = _as_complex(buf)
     return z[:n_lp], z[n_lp:n_lp + n_hp], z[n_lp + n_hp:], _stats_list(st)
 
 
 def tsm_estimate(lp_set_lp, hp_set_hp, hp_set_lp):
-    """The truncated solver method's estimate and its variance (FP64, host)."""
-    lp_set_lp, hp_set_hp, hp_set_lp = (np.asarray(a, dtype=np.complex128) for a in (lp_set_lp, hp_set_hp, hp_set_lp))
-    corr = hp_set_hp - hp_set_lp
-    est = lp_set_lp.mean(axis=0) + corr.mean(axis=0)
-    var = lp_set_lp.var(axis=0, ddof=1) / len(lp_set_lp) + corr.var(axis=0, ddof=1) / len(corr)
-    return est, var
+    """The truncated solver method's estimate and its variance (library, FP64): complex
+    [n_gamma][T] and real [n_gamma][T] from per-noise loops (complex [n][n_gamma][T])."""
+    lp, hh, hl = _as_pairs(lp_set_lp), _as_pairs(hp_set_hp), _as_pairs(hp_set_lp)
+    if lp.ndim != 4 or hh.shape != hl.shape or hh.shape[1:] != lp.shape[1:]:
+        raise ValueError("tsm_estimate: expected per-noise loops [n][n_gamma][T] with matching shapes")
+    n_gamma, T = lp.shape[1], lp.shape[2]
+    est = np.zeros((n_gamma, T, 2), dtype=np.float64)
+    var = np.zeros((n_gamma, T), dtype=np.float64)
+    dl_tsm_combine(lp, lp.shape[0], hh, hl, hh.shape[0], n_gamma, T, est, var)
+    return _as_complex(est), var
 
 
 def loops_dkappa(gauge: Gauge, kappa: float, sources: dl_sources, gammas, params=None, stream=None):
@@ -496,32 +543,31 @@ def loops_dkappa(gauge: Gauge, kappa: float, sources: dl_sources, gammas, params
     nrhs = dl_sources_count(gauge.lattice.h, sources)
     st = (dl_solve_stats * (2 * nrhs))()
     dl_loops_dkappa(gauge.h, kappa, sources, params, gammas, buf, st, stream)
-    return buf[..., 0] + 1j * buf[..., 1], _stats_list(st)
+    return _as_complex(buf), _stats_list(st)
 
 
 def loops_link_grad(gauge: Gauge, kappa: float, sources: dl_sources, gammas, w, params=None, with_dkappa=False,
-                    stream=None):
-    """Gradient of Re sum conj(w[n][g][t]) L[n][g][t] with respect to the links, complex [4][V][3][3]
+                    stream=None, grad_out=None):
+    """Gradient of F = Re sum conj(w[n][g][t]) L[n][g][t] with respect to the links, complex [4][V][3][3]
     (dF = Re sum conj(grad) dU); w is [n_noise][n_gamma][T] (or [n_gamma][T], the same for every
-    noise).  Returns (grad, loops, dloops or None, stats)."""
+    noise).  grad_out: None (a page-locked host array is returned) or a complex128 device tensor
+    [4][V][3][3] that receives the gradient.  Returns (grad, loops, dloops or None, dF/dkappa or None,
+    stats); with_dkappa adds the kappa derivative (a third solve per right-hand side)."""
     params = params or solve_params()
     T = gauge.lattice.dims[3]
     V = gauge.lattice.V
     n = int(sources.n_noise)
-    w = np.asarray(w, dtype=np.complex128)
-    if w.ndim == 2:
-        w = np.broadcast_to(w, (n,) + w.shape)
-    w = w.reshape(n, len(gammas), T)
-    wb = np.stack([w.real, w.imag], axis=-1)
-    grad = _pinned_host((4, V, 3, 3, 2))
+    wb = _as_pairs(np.reshape(np.asarray(w, dtype=np.complex128), (-1, len(gammas), T)), (n, len(gammas), T))
+    grad = _pinned_host((4, V, 3, 3, 2)) if grad_out is None else grad_out
     loops = np.zeros((n, len(gammas), T, 2), dtype=np.float64)
     dk = np.zeros((n, len(gammas), T, 2), dtype=np.float64) if with_dkappa else None
+    dfk = ctypes.c_double() if with_dkappa else None
     nrhs = dl_sources_count(gauge.lattice.h, sources)
     st = (dl_solve_stats * (3 * nrhs))()
-    dl_loops_link_grad(gauge.h, kappa, sources, params, gammas, wb, grad, loops, dk, st, stream)
-    # (re, im) pairs read as complex numbers in place
-    z = lambda a: None if a is None else a.view(np.complex128)[..., 0]  # noqa: E731
-    return z(grad), z(loops), z(dk), _stats_list(st)
+    dl_loops_link_grad(gauge.h, kappa, sources, params, gammas, wb, grad, loops, dk, dfk, st, stream)
+    g = _as_complex(grad) if grad_out is None else grad_out
+    return (g, _as_complex(loops), None if dk is None else _as_complex(dk), None if dfk is None else dfk.value,
+            _stats_list(st))
 
 
 def _pinned_host(shape):
@@ -543,4 +589,4 @@ def batch_loops(gauges, kappas, sources, gammas, params=None, stream=None):
         outs.append(np.zeros((int(src.n_noise), len(gammas), T, 2), dtype=np.float64))
         stats.append((dl_solve_stats * dl_sources_count(G.lattice.h, src))())
     dl_batch_loops([G.h for G in gauges], kappas, sources, params, gammas, outs, stats, stream)
-    return [o[..., 0] + 1j * o[..., 1] for o in outs], [_stats_list(s) for s in stats]
+    return [_as_complex(o) for o in outs], [_stats_list(s) for s in stats]

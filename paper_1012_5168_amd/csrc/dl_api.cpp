@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstdlib>
@@ -51,24 +52,38 @@ namespace dl {
 // mapping a fresh multi-GB allocation costs about as much as the solve it
 // serves, so released buffers are kept per (device, size) and handed out
 // again (a cached block serves a request of at least 4/5 of its size).  A
-// buffer enters the cache only after the device has finished every queued
-// kernel, as hipFree would have waited, so a later call on any stream cannot
-// race with work still reading it.  DL_CACHE_GB caps the cached bytes
-// (default 256; 0 turns the cache off); dl_cache_release frees all of it; an
-// allocation that fails releases the cache and tries again.
+// released block carries an event recorded on the stream of the call that
+// released it (every entry point names its stream, see StreamScope); a later
+// allocation that takes the block waits on that event, so no kernel still
+// reading or writing the block can race with its next user.  Where no call
+// stream is known the release synchronises the device instead, as hipFree
+// would.  The cached bytes are capped (DL_CACHE_GB, default 64 GB, or
+// dl_cache_set_limit; 0 turns the cache off); dl_cache_release frees all of
+// it; an allocation that fails releases the cache and tries again.
 namespace {
+struct CacheEntry {
+    void *p;
+    hipEvent_t ready;  // recorded after the block's last use (null: the device was synchronised)
+};
 std::mutex g_cache_mu;
-std::multimap<std::pair<int, size_t>, void *> g_cache_free;
+std::multimap<std::pair<int, size_t>, CacheEntry> g_cache_free;
 size_t g_cache_bytes = 0;
+bool g_cache_limit_set = false;
+size_t g_cache_limit = 0;
 
-size_t cache_cap()
+// the stream of the entry point running on this thread (StreamScope)
+thread_local bool t_stream_known = false;
+thread_local hipStream_t t_stream = nullptr;
+
+size_t cache_limit_locked()
 {
-    static const size_t cap = [] {
+    if (!g_cache_limit_set) {
         const char *e = std::getenv("DL_CACHE_GB");
-        const double gb = e ? std::atof(e) : 256.0;
-        return gb > 0 ? (size_t)(gb * 1073741824.0) : (size_t)0;
-    }();
-    return cap;
+        const double gb = e ? std::atof(e) : 64.0;
+        g_cache_limit = gb > 0 ? (size_t)(gb * 1073741824.0) : (size_t)0;
+        g_cache_limit_set = true;
+    }
+    return g_cache_limit;
 }
 
 int current_device()
@@ -78,39 +93,76 @@ int current_device()
     return d;
 }
 
-void cache_release_all_locked()
+void free_entry(const CacheEntry &c)
 {
-    if (g_cache_free.empty()) return;
-    (void)hipDeviceSynchronize();
-    for (auto &kv : g_cache_free) (void)hipFree(kv.second);
-    g_cache_free.clear();
-    g_cache_bytes = 0;
+    if (c.ready) {
+        (void)hipEventSynchronize(c.ready);
+        (void)hipEventDestroy(c.ready);
+    }
+    (void)hipFree(c.p);
+}
+
+// free cached blocks until at most `keep` bytes remain
+void cache_trim_locked(size_t keep)
+{
+    while (g_cache_bytes > keep && !g_cache_free.empty()) {
+        auto it = std::prev(g_cache_free.end());  // largest first
+        free_entry(it->second);
+        g_cache_bytes -= it->first.second;
+        g_cache_free.erase(it);
+    }
 }
 }  // namespace
+
+StreamScope::StreamScope(void *stream) : prev_known(t_stream_known), prev(t_stream)
+{
+    t_stream_known = true;
+    t_stream = static_cast<hipStream_t>(stream);
+}
+
+StreamScope::~StreamScope()
+{
+    t_stream_known = prev_known;
+    t_stream = static_cast<hipStream_t>(prev);
+}
 
 void DevBuf::alloc(size_t n)
 {
     release();
     if (n == 0) return;
     const int dev = current_device();
+    CacheEntry hit{nullptr, nullptr};
     {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         auto it = g_cache_free.lower_bound({dev, n});
         if (it != g_cache_free.end() && it->first.first == dev && it->first.second / 5 * 4 <= n) {
-            p = it->second;
+            hit = it->second;
             cap = it->first.second;
-            bytes = n;
             g_cache_bytes -= cap;
             g_cache_free.erase(it);
-            return;
         }
+    }
+    if (hit.p) {
+        if (hit.ready) {
+            // the block's previous user has finished with it
+            const hipError_t e = hipEventSynchronize(hit.ready);
+            (void)hipEventDestroy(hit.ready);
+            if (e != hipSuccess) {
+                (void)hipFree(hit.p);
+                cap = 0;
+                throw Error{DL_EHIP, std::string("waiting for a cached block: ") + hipGetErrorString(e)};
+            }
+        }
+        p = hit.p;
+        bytes = n;
+        return;
     }
     hipError_t e = hipMalloc(&p, n);
     if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
         (void)hipGetLastError();
         {
             std::lock_guard<std::mutex> lk(g_cache_mu);
-            cache_release_all_locked();
+            cache_trim_locked(0);
         }
         e = hipMalloc(&p, n);
     }
@@ -122,21 +174,48 @@ void DevBuf::alloc(size_t n)
     bytes = cap = n;
 }
 
-void DevBuf::release()
+void DevBuf::release() noexcept
 {
-    if (p) {
-        const size_t limit = cache_cap();
-        bool cached = false;
-        if (limit > 0) {
-            std::lock_guard<std::mutex> lk(g_cache_mu);
-            if (g_cache_bytes + cap <= limit && hipDeviceSynchronize() == hipSuccess) {
-                g_cache_free.insert({{current_device(), cap}, p});
-                g_cache_bytes += cap;
-                cached = true;
+    if (!p) return;
+    bool cached = false;
+    size_t limit = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        limit = cache_limit_locked();
+        if (g_cache_bytes + cap > limit) limit = 0;
+    }
+    if (limit > 0) {
+        CacheEntry c{p, nullptr};
+        bool idle = false;
+        if (t_stream_known && !capturing(t_stream)) {
+            if (hipEventCreateWithFlags(&c.ready, hipEventDisableTiming) == hipSuccess) {
+                if (hipEventRecord(c.ready, t_stream) == hipSuccess) {
+                    idle = true;
+                } else {
+                    (void)hipEventDestroy(c.ready);
+                    c.ready = nullptr;
+                }
+            } else {
+                c.ready = nullptr;
             }
         }
-        if (!cached) (void)hipFree(p);
+        if (!idle && !(t_stream_known && capturing(t_stream))) idle = hipDeviceSynchronize() == hipSuccess;
+        if (idle) {
+            try {
+                std::lock_guard<std::mutex> lk(g_cache_mu);
+                if (g_cache_bytes + cap <= cache_limit_locked()) {
+                    g_cache_free.insert({{current_device(), cap}, c});
+                    g_cache_bytes += cap;
+                    cached = true;
+                }
+            } catch (...) {
+                cached = false;
+            }
+        }
+        if (!cached && c.ready) (void)hipEventDestroy(c.ready);
     }
+    (void)hipGetLastError();
+    if (!cached) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
     cap = 0;
@@ -199,7 +278,7 @@ bool prof_on() { return g_prof_on; }
 
 unsigned *prof_counter()
 {
-    if (!g_prof_on) return nullptr;
+    if (!prof_on()) return nullptr;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     if (!g_prof_ctr.p) return nullptr;
     if (g_prof_next >= PROF_SLOTS) prof_drain_locked();
@@ -209,7 +288,7 @@ unsigned *prof_counter()
 ProfScope::ProfScope(int kind_, double bytes_, hipStream_t s_, int kind2_)
     : kind(kind_), kind2(kind2_), bytes(bytes_), s(s_)
 {
-    if (!g_prof_on || capturing(s)) return;
+    if (!prof_on() || capturing(s)) return;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         e0 = e1 = nullptr;
         return;
@@ -221,12 +300,19 @@ ProfScope::~ProfScope()
 {
     if (!e0) return;
     (void)hipEventRecord(e1, s);
-    std::lock_guard<std::mutex> lk(g_prof_mu);
-    ProfRec r{kind, kind2, bytes, e0, e1, {}};
-    for (const ProfPart &p : parts)
-        if (p.counter)
-            r.slots.push_back({(int)(p.counter - g_prof_ctr.as<unsigned>()), p.unit_bytes, p.fixed_bytes, p.units_div});
-    g_prof_pending.push_back(r);
+    try {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        ProfRec r{kind, kind2, bytes, e0, e1, {}};
+        for (const ProfPart &p : parts)
+            if (p.counter)
+                r.slots.push_back(
+                    {(int)(p.counter - g_prof_ctr.as<unsigned>()), p.unit_bytes, p.fixed_bytes, p.units_div});
+        g_prof_pending.push_back(r);
+    } catch (...) {
+        // out of host memory: this launch goes unrecorded (a destructor must not throw)
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
 }
 
 static void prof_drain_locked()
@@ -398,21 +484,48 @@ extern "C" int64_t dl_lattice_volume(dl_lattice lat) { return lat ? lat->V : 0; 
 
 // ====================================================================== gauge field
 
+namespace {
+
+// The gauge handle from the links staged on the device as [4][2][9][Vh]
+// complex128: each precision in prec_mask converted to its storage format.
+dl_gauge gauge_from_stage(const dl_lattice_s &lat, const DevBuf &stage, uint32_t prec_mask, int recon, hipStream_t s)
+{
+    auto G = std::make_unique<dl_gauge_s>();
+    G->lat = lat;
+    G->recon = recon;
+    G->prec_mask = prec_mask;
+    const int64_t Vh = G->lat.Vh;
+    const int ne = recon == 12 ? 6 : 9;
+    for (int p = 0; p < 4; ++p) {
+        if (!(prec_mask & (1u << p))) continue;
+        G->links[p].alloc((size_t)4 * 2 * ne * Vh * elem_bytes(p));
+        k_links_convert(p, G->links[p].p, ne, stage.as<double>(), Vh, s);
+    }
+    DL_HIP(hipGetLastError());
+    DL_HIP(hipStreamSynchronize(s));
+    return G.release();
+}
+
+void validate_gauge_args(dl_lattice lat, const void *links, uint32_t prec_mask, int32_t recon, dl_gauge *out,
+                         const char *who)
+{
+    DL_REQUIRE(lat && links && out, std::string(who) + ": null pointer");
+    DL_REQUIRE((prec_mask & 0xF) != 0 && (prec_mask & ~0xFu) == 0,
+               std::string(who) + ": prec_mask must be a non-empty subset of bits 0..3");
+    DL_REQUIRE(recon == 12 || recon == 18, std::string(who) + ": recon must be 12 or 18");
+}
+
+}  // namespace
+
 extern "C" int dl_gauge_create(dl_lattice lat, const double *links, uint32_t prec_mask, int32_t recon, void *stream,
                                dl_gauge *out)
 {
     return guarded([&]() {
-        DL_REQUIRE(lat && links && out, "dl_gauge_create: null pointer");
-        DL_REQUIRE((prec_mask & 0xF) != 0 && (prec_mask & ~0xFu) == 0, "dl_gauge_create: prec_mask must be a "
-                                                                        "non-empty subset of bits 0..3");
-        DL_REQUIRE(recon == 12 || recon == 18, "dl_gauge_create: recon must be 12 or 18");
+        StreamScope scope(stream);
+        validate_gauge_args(lat, links, prec_mask, recon, out, "dl_gauge_create");
         hipStream_t s = static_cast<hipStream_t>(stream);
-        auto G = std::make_unique<dl_gauge_s>();
-        G->lat = *lat;
-        G->recon = recon;
-        G->prec_mask = prec_mask;
-        const Geom g = G->lat.geom();
-        const int64_t V = G->lat.V, Vh = G->lat.Vh;
+        const Geom g = lat->geom();
+        const int64_t V = lat->V, Vh = lat->Vh;
         // host reorder: canonical [mu][V][3][3] -> [mu][parity][9][Vh]
         std::vector<double> re((size_t)4 * 2 * 9 * Vh * 2);
         for (int64_t i = 0; i < V; ++i) {
@@ -435,15 +548,21 @@ extern "C" int dl_gauge_create(dl_lattice lat, const double *links, uint32_t pre
         }
         DevBuf stage(re.size() * sizeof(double));
         DL_HIP(hipMemcpyAsync(stage.p, re.data(), stage.bytes, hipMemcpyHostToDevice, s));
-        const int ne = recon == 12 ? 6 : 9;
-        for (int p = 0; p < 4; ++p) {
-            if (!(prec_mask & (1u << p))) continue;
-            G->links[p].alloc((size_t)4 * 2 * ne * Vh * elem_bytes(p));
-            k_links_convert(p, G->links[p].p, ne, stage.as<double>(), Vh, s);
-        }
-        DL_HIP(hipGetLastError());
-        DL_HIP(hipStreamSynchronize(s));
-        *out = G.release();
+        *out = gauge_from_stage(*lat, stage, prec_mask, recon, s);
+        return DL_OK;
+    });
+}
+
+extern "C" int dl_gauge_create_device(dl_lattice lat, const void *links, uint32_t prec_mask, int32_t recon,
+                                      void *stream, dl_gauge *out)
+{
+    return guarded([&]() {
+        StreamScope scope(stream);
+        validate_gauge_args(lat, links, prec_mask, recon, out, "dl_gauge_create_device");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        DevBuf stage((size_t)4 * 2 * 9 * lat->Vh * 16);
+        k_links_reorder(static_cast<const double *>(links), stage.as<double>(), lat->geom(), s);
+        *out = gauge_from_stage(*lat, stage, prec_mask, recon, s);
         return DL_OK;
     });
 }
@@ -530,15 +649,60 @@ void check_prec(dl_gauge G, int prec)
 
 }  // namespace
 
+namespace {
+
+void validate_apply(dl_gauge G, int32_t op, int32_t prec, const void *in, void *out, int64_t nrhs, const char *who)
+{
+    DL_REQUIRE(G && in && out, std::string(who) + ": null pointer");
+    DL_REQUIRE(nrhs >= 1 && nrhs <= 65535, std::string(who) + ": nrhs must be in [1, 65535]");
+    DL_REQUIRE(op >= DL_OP_DHOP && op <= DL_OP_DHOPDAG, std::string(who) + ": unknown operator");
+    check_prec(G, prec);
+    DL_REQUIRE(in != out, std::string(who) + ": in and out must not overlap");
+}
+
+bool schur_op(int op) { return op == DL_OP_MHAT || op == DL_OP_MHATDAG; }
+
+// The launches of dl_apply on packed parity fields: ie / io receive the packed
+// input, oe / oo the output, tmp (Schur operators only) the odd-site
+// intermediate.  Every field is written before it is read; the odd output of
+// a Schur operator is cleared.
+void apply_op(const Ctx &c, int op, int prec, double kappa, const void *in, void *out, int n, Field ie, Field io,
+              Field oe, Field oo, Field tmp)
+{
+    const int64_t Vh = c.G->lat.Vh;
+    k_pack(prec, ie, 0, static_cast<const double *>(in), c.g, n, c.s);
+    k_pack(prec, io, 1, static_cast<const double *>(in), c.g, n, c.s);
+    const bool dag = op == DL_OP_MDAG || op == DL_OP_MHATDAG || op == DL_OP_DHOPDAG;
+    switch (op) {
+    case DL_OP_DHOP:
+    case DL_OP_DHOPDAG:
+        launch_dslash(dcall(c, prec, 0, dag, EPI_PLAIN, io, oe, NOF, NOF, 1.0, n, nullptr, nullptr), c.s);
+        launch_dslash(dcall(c, prec, 1, dag, EPI_PLAIN, ie, oo, NOF, NOF, 1.0, n, nullptr, nullptr), c.s);
+        break;
+    case DL_OP_M:
+    case DL_OP_MDAG:
+        launch_dslash(dcall(c, prec, 0, dag, EPI_XPAY, io, oe, ie, NOF, -kappa, n, nullptr, nullptr), c.s);
+        launch_dslash(dcall(c, prec, 1, dag, EPI_XPAY, ie, oo, io, NOF, -kappa, n, nullptr, nullptr), c.s);
+        break;
+    default:  // Schur complement on even sites
+        launch_dslash(dcall(c, prec, 1, dag, EPI_PLAIN, ie, tmp, NOF, NOF, 1.0, n, nullptr, nullptr), c.s);
+        launch_dslash(dcall(c, prec, 0, dag, EPI_XPAY, tmp, oe, ie, NOF, -kappa * kappa, n, nullptr, nullptr), c.s);
+        vec_launch(V_ZERO, prec, {VSeg{{oo, NOF, NOF, NOF, NOF}, nullptr, nullptr, Vh, n, nullptr}}, c.s);
+        break;
+    }
+    k_unpack(prec, oe, 0, static_cast<double *>(out), c.g, n, c.s);
+    k_unpack(prec, oo, 1, static_cast<double *>(out), c.g, n, c.s);
+    DL_HIP(hipGetLastError());
+}
+
+}  // namespace
+
 extern "C" int dl_apply(dl_gauge G, double kappa, int32_t op, int32_t prec, const void *in, void *out, int64_t nrhs,
                         void *stream)
 {
     return guarded([&]() {
-        DL_REQUIRE(G && in && out, "dl_apply: null pointer");
-        DL_REQUIRE(nrhs >= 1 && nrhs <= 65535, "dl_apply: nrhs must be in [1, 65535]");
-        DL_REQUIRE(op >= DL_OP_DHOP && op <= DL_OP_DHOPDAG, "dl_apply: unknown operator");
-        check_prec(G, prec);
-        DL_REQUIRE(in != out, "dl_apply: in and out must not overlap");
+        StreamScope scope(stream);
+        validate_apply(G, op, prec, in, out, nrhs, "dl_apply");
         Ctx c{G, G->lat.geom(), static_cast<hipStream_t>(stream)};
         const int n = (int)nrhs;
         const int64_t Vh = G->lat.Vh;
@@ -547,39 +711,8 @@ extern "C" int dl_apply(dl_gauge G, double kappa, int32_t op, int32_t prec, cons
         io.alloc(prec, n, Vh);
         oe.alloc(prec, n, Vh);
         oo.alloc(prec, n, Vh);
-        k_pack(prec, ie.view(), 0, static_cast<const double *>(in), c.g, n, c.s);
-        k_pack(prec, io.view(), 1, static_cast<const double *>(in), c.g, n, c.s);
-        const bool dag = op == DL_OP_MDAG || op == DL_OP_MHATDAG || op == DL_OP_DHOPDAG;
-        switch (op) {
-        case DL_OP_DHOP:
-        case DL_OP_DHOPDAG:
-            launch_dslash(dcall(c, prec, 0, dag, EPI_PLAIN, io.view(), oe.view(), NOF, NOF, 1.0, n, nullptr, nullptr),
-                          c.s);
-            launch_dslash(dcall(c, prec, 1, dag, EPI_PLAIN, ie.view(), oo.view(), NOF, NOF, 1.0, n, nullptr, nullptr),
-                          c.s);
-            break;
-        case DL_OP_M:
-        case DL_OP_MDAG:
-            launch_dslash(
-                dcall(c, prec, 0, dag, EPI_XPAY, io.view(), oe.view(), ie.view(), NOF, -kappa, n, nullptr, nullptr),
-                c.s);
-            launch_dslash(
-                dcall(c, prec, 1, dag, EPI_XPAY, ie.view(), oo.view(), io.view(), NOF, -kappa, n, nullptr, nullptr),
-                c.s);
-            break;
-        default:  // Schur complement on even sites
-            tmp.alloc(prec, n, Vh);
-            launch_dslash(dcall(c, prec, 1, dag, EPI_PLAIN, ie.view(), tmp.view(), NOF, NOF, 1.0, n, nullptr, nullptr),
-                          c.s);
-            launch_dslash(dcall(c, prec, 0, dag, EPI_XPAY, tmp.view(), oe.view(), ie.view(), NOF, -kappa * kappa, n,
-                                nullptr, nullptr),
-                          c.s);
-            vec_launch(V_ZERO, prec, {VSeg{{oo.view(), NOF, NOF, NOF, NOF}, nullptr, nullptr, Vh, n, nullptr}}, c.s);
-            break;
-        }
-        k_unpack(prec, oe.view(), 0, static_cast<double *>(out), c.g, n, c.s);
-        k_unpack(prec, oo.view(), 1, static_cast<double *>(out), c.g, n, c.s);
-        DL_HIP(hipGetLastError());
+        if (schur_op(op)) tmp.alloc(prec, n, Vh);
+        apply_op(c, op, prec, kappa, in, out, n, ie.view(), io.view(), oe.view(), oo.view(), tmp.view());
         DL_HIP(hipStreamSynchronize(c.s));
         return DL_OK;
     });
@@ -811,10 +944,13 @@ int count_all(const std::vector<Prob> &P, bool upd, hipStream_t s)
 }
 
 // A stream that graph capture may use: the caller's stream unless it is the
-// legacy default stream, else a library stream ordered after it.
+// legacy default stream, else a library stream ordered after it.  The
+// caller's stream is ordered after the library stream again by join(), or by
+// the destructor when an error unwinds the solve first.
 struct CaptureStream {
     hipStream_t user, s;
     hipEvent_t ev = nullptr;
+    bool joined = false;
     explicit CaptureStream(hipStream_t u) : user(u), s(u)
     {
         if (u != nullptr) return;
@@ -829,15 +965,67 @@ struct CaptureStream {
     }
     void join()
     {
-        if (s == user) return;
+        if (s == user || joined) return;
         DL_HIP(hipEventRecord(ev, s));
         DL_HIP(hipStreamWaitEvent(user, ev, 0));
+        joined = true;
     }
+    CaptureStream(const CaptureStream &) = delete;
+    CaptureStream &operator=(const CaptureStream &) = delete;
     ~CaptureStream()
     {
+        if (s != user && !joined && ev) {
+            (void)hipEventRecord(ev, s);
+            (void)hipStreamWaitEvent(user, ev, 0);
+        }
         if (ev) (void)hipEventDestroy(ev);
     }
 };
+
+// The captured graph of one chunk of iterations.  A capture still open is
+// ended and the graph and its executable are destroyed on every exit,
+// including an error thrown between the start of a capture and its
+// instantiation, so the stream is left usable for the caller.
+struct ChunkGraph {
+    hipStream_t s = nullptr;
+    bool open = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ChunkGraph() = default;
+    ChunkGraph(const ChunkGraph &) = delete;
+    ChunkGraph &operator=(const ChunkGraph &) = delete;
+    void begin(hipStream_t st)
+    {
+        s = st;
+        DL_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        open = true;
+    }
+    void end()
+    {
+        open = false;  // the stream leaves capture mode whatever EndCapture returns
+        DL_HIP(hipStreamEndCapture(s, &graph));
+        DL_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    }
+    ~ChunkGraph()
+    {
+        if (open) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(s, &g);
+            if (g) (void)hipGraphDestroy(g);
+        }
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+    }
+};
+
+// Failure injection for the tests of the error paths: DL_FAULT_INJECT=capture
+// makes a graph capture throw after it has begun (read at every capture).
+bool fault_injected(const char *where)
+{
+    const char *e = std::getenv("DL_FAULT_INJECT");
+    return e != nullptr && std::strcmp(e, where) == 0;
+}
 
 // BiCGStab on the even-site Schur systems of every problem (sources in w.be /
 // w.bo, FP64).  Leaves x_e in w.x64, x_o in w.xo and the per right-hand side
@@ -897,18 +1085,17 @@ void bicgstab_multi(const std::vector<Prob> &P0, const dl_solve_params &prm, hip
     const int poll = parse_poll(prm);
     int it = 0;
     const int cap = prm.maxiter + poll + 8;
-    hipGraphExec_t exec = nullptr;
-    hipGraph_t graph = nullptr;
+    ChunkGraph cg;
     bool first_chunk = true;
     while (it < cap) {
         if (prm.use_graph && !first_chunk) {
-            if (!exec) {
-                DL_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            if (!cg.exec) {
+                cg.begin(s);
+                if (fault_injected("capture")) throw Error{DL_EHIP, "injected fault inside a graph capture"};
                 for (int k = 0; k < poll; ++k) bicg_iteration(P, prec, mixed, s);
-                DL_HIP(hipStreamEndCapture(s, &graph));
-                DL_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+                cg.end();
             }
-            DL_HIP(hipGraphLaunch(exec, s));
+            DL_HIP(hipGraphLaunch(cg.exec, s));
             it += poll;
         } else {
             // the first chunk runs eagerly: it tunes every launch shape the graph will use
@@ -965,8 +1152,6 @@ void bicgstab_multi(const std::vector<Prob> &P0, const dl_solve_params &prm, hip
         }
         if (count_all(P, false, s) == 0) break;
     }
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
     // x_o = b_o + kappa D_oe x_e
     launch_dslash_batch(DS(P, [&](const Prob &p) {
                             return dcall(p.c, P64, 1, false, EPI_XPAY, p.w->x64.view(), p.w->xo.view(), p.w->bo.view(),
@@ -1105,12 +1290,50 @@ int batch_size(size_t per_rhs, int64_t total, int quantum)
     return (int)std::min<int64_t>(std::min<int64_t>(b, even), total);
 }
 
+// Wall time of the parts of a call, for the per-right-hand-side seconds of
+// the solve statistics.
+struct Stopwatch {
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    double lap()  // seconds since the previous lap (or since construction)
+    {
+        const auto t = std::chrono::steady_clock::now();
+        const double d = std::chrono::duration<double>(t - t0).count();
+        t0 = t;
+        return d;
+    }
+};
+
+// Algorithmic bytes of one right-hand side's field operands in a solve: every
+// operand of every kernel the solve runs for it, moved once (the links, which
+// the whole batch shares, are not counted).  Per iteration: BiCGStab moves 25
+// half fields in the iteration precision (the p update 4, two plain hops 2
+// each, the hop with the (rhat, v) dot 4, the s update 3, the hop with the
+// (t, s) and |t|^2 sums 3, the x and r update with its sums 7); the truncated
+// CGNR 19 (four hops 2 + 3 + 2 + 4, the r update 3, the fused x and p update
+// 5).  A reliable update moves 8 FP64 half fields (two for the fold, 2 + 4
+// for the FP64 residual hops, one for the copy back) and 3 in the iteration
+// precision; the set-up 12 FP64 and 7 iteration-precision half fields
+// (source norms, prepared source, zeroed vectors, the first dot) and the
+// reconstruction of the odd sites 3 FP64 half fields.
+double solve_bytes(const SolveWork &w, const KState &k, bool cgnr)
+{
+    const double vh = (double)w.r.Vh;
+    const double fb = vh * (12.0 * elem_bytes(w.prec) + (w.prec == P16 ? 4.0 : 0.0));
+    if (cgnr) return k.iters * 19.0 * fb + 8.0 * fb;
+    const double f8 = vh * 12.0 * 16.0;
+    return k.iters * 25.0 * fb + k.updates * (8.0 * f8 + 3.0 * fb) + 15.0 * f8 + 7.0 * fb;
+}
+
+// Per right-hand side statistics of the solve just finished; `seconds` is the
+// solve's share of the wall time since the stopwatch's last lap (the batch's
+// time divided by its right-hand sides).
 void fill_stats(const SolveWork &w, const std::vector<double> &res2, dl_solve_stats *out, hipStream_t s,
-                bool cgnr)
+                bool cgnr, Stopwatch &sw, double secs_per_rhs = -1.0)
 {
     std::vector<KState> h(w.n);
     DL_HIP(hipMemcpyAsync(h.data(), w.st.p, sizeof(KState) * w.n, hipMemcpyDeviceToHost, s));
     DL_HIP(hipStreamSynchronize(s));
+    const double secs = secs_per_rhs >= 0 ? secs_per_rhs : sw.lap() / std::max(1, w.n);
     for (int i = 0; i < w.n; ++i) {
         dl_solve_stats &o = out[i];
         o.iters = h[i].iters;
@@ -1124,6 +1347,8 @@ void fill_stats(const SolveWork &w, const std::vector<double> &res2, dl_solve_st
             o.status = DL_OK;
         else
             o.status = DL_ENOCONV;
+        o.seconds = secs;
+        o.bytes = solve_bytes(w, h[i], cgnr);
     }
 }
 
@@ -1133,6 +1358,7 @@ extern "C" int dl_solve(dl_gauge G, double kappa, const dl_solve_params *params,
                         dl_solve_stats *stats, void *stream)
 {
     return guarded([&]() {
+        StreamScope scope(stream);
         DL_REQUIRE(G && b && x, "dl_solve: null pointer");
         DL_REQUIRE(nrhs >= 1, "dl_solve: nrhs must be >= 1");
         DL_REQUIRE(b != x, "dl_solve: b and x must not overlap");
@@ -1146,6 +1372,7 @@ extern "C" int dl_solve(dl_gauge G, double kappa, const dl_solve_params *params,
         const size_t per = cg ? SolveWork::bytes_cgnr(prm.prec, Vh) : SolveWork::bytes_bicg(prm.prec, Vh);
         const int B = batch_size(per, nrhs, 1);
         int worst = DL_OK;
+        Stopwatch sw;
         for (int64_t r0 = 0; r0 < nrhs; r0 += B) {
             const int n = (int)std::min<int64_t>(B, nrhs - r0);
             SolveWork w;
@@ -1171,7 +1398,7 @@ extern "C" int dl_solve(dl_gauge G, double kappa, const dl_solve_params *params,
             DL_HIP(hipGetLastError());
             DL_HIP(hipStreamSynchronize(c.s));
             std::vector<dl_solve_stats> st(n);
-            fill_stats(w, res2, st.data(), c.s, cg);
+            fill_stats(w, res2, st.data(), c.s, cg, sw);
             for (int i = 0; i < n; ++i) {
                 if (stats) stats[r0 + i] = st[i];
                 if (st[i].status != DL_OK && worst == DL_OK) worst = st[i].status;
@@ -1232,6 +1459,7 @@ extern "C" int dl_sources_fill(dl_lattice lat, const dl_sources *src, int64_t fi
                                void *stream)
 {
     return guarded([&]() {
+        StreamScope scope(stream);
         DL_REQUIRE(lat && out, "dl_sources_fill: null pointer");
         validate_sources(*lat, src);
         const int ncls = source_classes(src);
@@ -1348,6 +1576,7 @@ int loops_run(dl_gauge G, double kappa, const dl_sources *src, const dl_solve_pa
         k_zero(P64, Field{dgrad.p, nullptr}, (int64_t)4 * V * 9 / 12, 1, nullptr, c.s);  // [4][V][9] complex
     }
     int worst = DL_OK;
+    Stopwatch sw;
     std::vector<int64_t> hnoise;
     std::vector<int> hcls;
     for (int64_t r0 = 0; r0 < total; r0 += B) {
@@ -1409,14 +1638,14 @@ int loops_run(dl_gauge G, double kappa, const dl_sources *src, const dl_solve_pa
             make_source(prm.prec, w.be.view(), w.bo.view());
             cgnr_batch(c, kappa, prm.fixed_iters, w);
             sol_prec = prm.prec;
-            fill_stats(w, {}, st[0].data(), c.s, true);
+            fill_stats(w, {}, st[0].data(), c.s, true, sw);
         } else {
             std::vector<double> res2;
             w.alloc_bicg(prm.prec, n, Vh);
             make_source(P64, w.be.view(), w.bo.view());
             bicgstab_batch(c, kappa, prm, w);
             if (stats) true_residual_full(c, kappa, w, res2);
-            fill_stats(w, res2, st[0].data(), c.s, false);
+            fill_stats(w, res2, st[0].data(), c.s, false, sw);
             if (mode == MODE_DKAPPA) {
                 // second solve on w = D s (sources are regenerated for the trace)
                 launch_dslash(dcall(c, P64, 0, false, EPI_PLAIN, w.xo.view(), w.be.view(), NOF, NOF, 1.0, n, nullptr,
@@ -1428,7 +1657,7 @@ int loops_run(dl_gauge G, double kappa, const dl_sources *src, const dl_solve_pa
                 bicgstab_batch(c, kappa, prm, w);
                 res2.clear();
                 if (stats) true_residual_full(c, kappa, w, res2);
-                fill_stats(w, res2, st[1].data(), c.s, false);
+                fill_stats(w, res2, st[1].data(), c.s, false, sw);
             } else if (mode == MODE_GRAD) {
                 HalfField se, so;
                 se.alloc(P64, n, Vh);
@@ -1451,7 +1680,7 @@ int loops_run(dl_gauge G, double kappa, const dl_sources *src, const dl_solve_pa
                     bicgstab_batch(c, kappa, prm, w);
                     res2.clear();
                     if (stats) true_residual_full(c, kappa, w, res2);
-                    fill_stats(w, res2, st[2].data(), c.s, false);
+                    fill_stats(w, res2, st[2].data(), c.s, false, sw);
                     k_trace(P64, w.x64.view(), w.xo.view(), ss, c.g, n, dC.as<double>(), c.s);
                     k_gamma_contract(dC.as<double>(), nn, ncls, T, dgam.as<double>(), dgidx.as<int>(), n_gamma,
                                      ddk.as<double>() + (r0 / ncls) * n_gamma * T * 2, c.s);
@@ -1462,7 +1691,7 @@ int loops_run(dl_gauge G, double kappa, const dl_sources *src, const dl_solve_pa
                 bicgstab_batch(c, kappa, prm, w);
                 res2.clear();
                 if (stats) true_residual_full(c, kappa, w, res2);
-                fill_stats(w, res2, st[1].data(), c.s, false);
+                fill_stats(w, res2, st[1].data(), c.s, false, sw);
                 k_link_grad(se.view(), so.view(), w.x64.view(), w.xo.view(), c.g, n, kappa, dgrad.as<double>(),
                             c.s);
                 DL_HIP(hipStreamSynchronize(c.s));
@@ -1482,7 +1711,7 @@ int loops_run(dl_gauge G, double kappa, const dl_sources *src, const dl_solve_pa
             }
     }
     if (out_host) DL_HIP(hipMemcpyAsync(out_host, dloops.p, dloops.bytes, hipMemcpyDeviceToHost, c.s));
-    if (grad_host) DL_HIP(hipMemcpyAsync(grad_host, dgrad.p, dgrad.bytes, hipMemcpyDeviceToHost, c.s));
+    if (grad_host) DL_HIP(hipMemcpyAsync(grad_host, dgrad.p, dgrad.bytes, hipMemcpyDefault, c.s));
     if (dout_host) DL_HIP(hipMemcpyAsync(dout_host, ddk.p, ddk.bytes, hipMemcpyDeviceToHost, c.s));
     DL_HIP(hipStreamSynchronize(c.s));
     if (worst != DL_OK) g_err = "at least one solve did not converge";
@@ -1501,6 +1730,7 @@ extern "C" int dl_loops(dl_gauge G, double kappa, const dl_sources *src, const d
                         const int32_t *gammas, int32_t n_gamma, double *loops, dl_solve_stats *stats, void *stream)
 {
     return guarded([&]() {
+        StreamScope scope(stream);
         DL_REQUIRE(G && loops, "dl_loops: null pointer");
         validate_sources(G->lat, src);
         validate_params(params);
@@ -1516,6 +1746,7 @@ extern "C" int dl_loops_smeared(dl_gauge G, double kappa, const dl_sources *src,
                                 dl_solve_stats *stats, void *stream)
 {
     return guarded([&]() {
+        StreamScope scope(stream);
         DL_REQUIRE(G && loops, "dl_loops_smeared: null pointer");
         validate_sources(G->lat, src);
         validate_params(params);
@@ -1533,6 +1764,7 @@ extern "C" int dl_smear(dl_gauge G, double alpha, int32_t iters, const void *in,
                         void *stream)
 {
     return guarded([&]() {
+        StreamScope scope(stream);
         DL_REQUIRE(G && in && out, "dl_smear: null pointer");
         DL_REQUIRE(nrhs >= 1 && nrhs <= 65535, "dl_smear: nrhs must be in [1, 65535]");
         DL_REQUIRE(std::isfinite(alpha) && alpha >= 0, "dl_smear: alpha must be finite and >= 0");
@@ -1568,6 +1800,7 @@ extern "C" int dl_loops_tsm(dl_gauge G, double kappa, const dl_sources *src, con
                             void *stream)
 {
     return guarded([&]() {
+        StreamScope scope(stream);
         DL_REQUIRE(G && loops && tsm, "dl_loops_tsm: null pointer");
         validate_sources(G->lat, src);
         DL_REQUIRE(src->kind == DL_SRC_Z2, "dl_loops_tsm: needs noise sources");
@@ -1609,6 +1842,7 @@ extern "C" int dl_loops_dkappa(dl_gauge G, double kappa, const dl_sources *src, 
                                void *stream)
 {
     return guarded([&]() {
+        StreamScope scope(stream);
         DL_REQUIRE(G && dloops, "dl_loops_dkappa: null pointer");
         validate_sources(G->lat, src);
         validate_params(params);
@@ -1622,17 +1856,80 @@ extern "C" int dl_loops_dkappa(dl_gauge G, double kappa, const dl_sources *src, 
 
 extern "C" int dl_loops_link_grad(dl_gauge G, double kappa, const dl_sources *src, const dl_solve_params *params,
                                   const int32_t *gammas, int32_t n_gamma, const double *w, double *grad,
-                                  double *loops, double *dloops, dl_solve_stats *stats, void *stream)
+                                  double *loops, double *dloops, double *dF_dkappa, dl_solve_stats *stats,
+                                  void *stream)
 {
     return guarded([&]() {
+        StreamScope scope(stream);
         DL_REQUIRE(G && w && grad, "dl_loops_link_grad: null pointer");
         validate_sources(G->lat, src);
         validate_params(params);
         DL_REQUIRE(params->solver == DL_BICGSTAB, "dl_loops_link_grad: needs the tolerance-driven BiCGStab");
         validate_gammas(gammas, n_gamma);
         check_solver_for(G, *params);
-        return loops_run(G, kappa, src, *params, gammas, n_gamma, MODE_GRAD, w, loops, grad, stats,
-                         static_cast<hipStream_t>(stream), dloops);
+        const size_t m = (size_t)src->n_noise * n_gamma * G->lat.dims[3] * 2;
+        std::vector<double> dk_own;
+        double *dk = dloops;
+        if (dF_dkappa && !dk) {
+            dk_own.resize(m);
+            dk = dk_own.data();
+        }
+        const int rc = loops_run(G, kappa, src, *params, gammas, n_gamma, MODE_GRAD, w, loops, grad, stats,
+                                 static_cast<hipStream_t>(stream), dk);
+        if (dF_dkappa) {
+            // dF/dkappa = Re sum conj(w) dL/dkappa, in a fixed order
+            double acc = 0.0;
+            for (size_t k = 0; k < m; k += 2) acc += w[k] * dk[k] + w[k + 1] * dk[k + 1];
+            *dF_dkappa = acc;
+        }
+        return rc;
+    });
+}
+
+extern "C" int dl_tsm_combine(const double *lp_set_lp, int32_t n_lp, const double *hp_set_hp,
+                              const double *hp_set_lp, int32_t n_hp, int32_t n_gamma, int32_t T, double *est,
+                              double *var)
+{
+    return guarded([&]() {
+        DL_REQUIRE(lp_set_lp && hp_set_hp && hp_set_lp && est, "dl_tsm_combine: null pointer");
+        DL_REQUIRE(n_gamma >= 1 && n_gamma <= 16, "dl_tsm_combine: n_gamma must be in [1, 16]");
+        DL_REQUIRE(T >= 1 && T <= 65535, "dl_tsm_combine: T must be in [1, 65535]");
+        DL_REQUIRE(n_lp >= 1 && n_hp >= 1, "dl_tsm_combine: both noise sets must be non-empty");
+        DL_REQUIRE(!var || (n_lp >= 2 && n_hp >= 2),
+                   "dl_tsm_combine: the variance needs at least two noises in each set");
+        const size_t m = (size_t)n_gamma * T;
+        for (size_t k = 0; k < m; ++k) {
+            // mean of the low-precision set and of the high-minus-low corrections
+            double lr = 0, li = 0, cr = 0, ci = 0;
+            for (int j = 0; j < n_lp; ++j) {
+                lr += lp_set_lp[(j * m + k) * 2];
+                li += lp_set_lp[(j * m + k) * 2 + 1];
+            }
+            for (int j = 0; j < n_hp; ++j) {
+                cr += hp_set_hp[(j * m + k) * 2] - hp_set_lp[(j * m + k) * 2];
+                ci += hp_set_hp[(j * m + k) * 2 + 1] - hp_set_lp[(j * m + k) * 2 + 1];
+            }
+            lr /= n_lp;
+            li /= n_lp;
+            cr /= n_hp;
+            ci /= n_hp;
+            est[2 * k] = lr + cr;
+            est[2 * k + 1] = li + ci;
+            if (!var) continue;
+            // unbiased sample variances of the two means (|z - mean|^2 summed, over n - 1)
+            double sl = 0, sc = 0;
+            for (int j = 0; j < n_lp; ++j) {
+                const double dr = lp_set_lp[(j * m + k) * 2] - lr, di = lp_set_lp[(j * m + k) * 2 + 1] - li;
+                sl += dr * dr + di * di;
+            }
+            for (int j = 0; j < n_hp; ++j) {
+                const double dr = hp_set_hp[(j * m + k) * 2] - hp_set_lp[(j * m + k) * 2] - cr;
+                const double di = hp_set_hp[(j * m + k) * 2 + 1] - hp_set_lp[(j * m + k) * 2 + 1] - ci;
+                sc += dr * dr + di * di;
+            }
+            var[k] = sl / (n_lp - 1) / n_lp + sc / (n_hp - 1) / n_hp;
+        }
+        return DL_OK;
     });
 }
 
@@ -1643,6 +1940,7 @@ extern "C" int dl_batch_loops(int32_t n_lat, const dl_gauge *gauges, const doubl
                               double *const *loops, dl_solve_stats *const *stats, void *stream)
 {
     return guarded([&]() {
+        StreamScope scope(stream);
         DL_REQUIRE(n_lat >= 1 && n_lat <= MAXSEG, "dl_batch_loops: n_lat must be in [1, 4]");
         DL_REQUIRE(gauges && kappas && srcs && loops, "dl_batch_loops: null pointer");
         validate_params(params);
@@ -1674,6 +1972,7 @@ extern "C" int dl_batch_loops(int32_t n_lat, const dl_gauge *gauges, const doubl
         for (int l = 0; l < n_lat; ++l)
             dloops[l].alloc((size_t)srcs[l].n_noise * n_gamma * gauges[l]->lat.dims[3] * 2 * sizeof(double));
         int worst = DL_OK;
+        Stopwatch sw;
         for (int n0 = 0; n0 < max_noise; n0 += k) {
             std::vector<std::unique_ptr<SolveWork>> work;
             std::vector<DevBuf> dnoise, dcls, dC;
@@ -1718,6 +2017,10 @@ extern "C" int dl_batch_loops(int32_t n_lat, const dl_gauge *gauges, const doubl
                 n_of.push_back(nn);
             }
             bicgstab_multi(P, prm, s);
+            DL_HIP(hipStreamSynchronize(s));
+            int round_rhs = 0;
+            for (const Prob &p : P) round_rhs += p.w->n;
+            const double secs_per_rhs = sw.lap() / std::max(1, round_rhs);
             for (size_t q = 0; q < P.size(); ++q) {
                 const int l = lat_of[q];
                 SolveWork &w = *P[q].w;
@@ -1729,7 +2032,7 @@ extern "C" int dl_batch_loops(int32_t n_lat, const dl_gauge *gauges, const doubl
                 k_gamma_contract(dC[q].as<double>(), n_of[q], ncls, T, dgam.as<double>(), dgidx.as<int>(), n_gamma,
                                  dloops[l].as<double>() + (size_t)n0 * n_gamma * T * 2, s);
                 std::vector<dl_solve_stats> st(w.n);
-                fill_stats(w, res2, st.data(), s, false);
+                fill_stats(w, res2, st.data(), s, false, sw, secs_per_rhs);
                 for (int i = 0; i < w.n; ++i) {
                     if (stats && stats[l]) stats[l][(int64_t)n0 * ncls + i] = st[i];
                     if (st[i].status != DL_OK && worst == DL_OK) worst = st[i].status;
@@ -1752,6 +2055,7 @@ extern "C" int dl_disconnected_correlator(const double *loops_b, const double *l
                                           int64_t spatial_volume, double *corr, void *stream)
 {
     return guarded([&]() {
+        StreamScope scope(stream);
         DL_REQUIRE(loops_b && loops_a && corr, "dl_disconnected_correlator: null pointer");
         DL_REQUIRE(n_noise >= 2, "dl_disconnected_correlator: needs at least two noises");
         DL_REQUIRE(T >= 1 && T <= 65535, "dl_disconnected_correlator: T must be in [1, 65535]");
@@ -1788,9 +2092,26 @@ extern "C" int dl_cache_release(void)
 {
     return guarded([&]() {
         std::lock_guard<std::mutex> lk(g_cache_mu);
-        cache_release_all_locked();
+        cache_trim_locked(0);
         return DL_OK;
     });
+}
+
+extern "C" int dl_cache_set_limit(uint64_t bytes)
+{
+    return guarded([&]() {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        g_cache_limit = (size_t)bytes;
+        g_cache_limit_set = true;
+        cache_trim_locked(g_cache_limit);
+        return DL_OK;
+    });
+}
+
+extern "C" uint64_t dl_cache_bytes(void)
+{
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    return (uint64_t)g_cache_bytes;
 }
 
 // ====================================================================== profiling API

@@ -437,6 +437,28 @@ __global__ __launch_bounds__(BS) void links_convert_kernel(void *dst, int ne, co
     }
 }
 
+// canonical links [4][V][9] complex128 (site i = x + X (y + Y (z + Z t))) ->
+// [4][2][9][Vh] complex128, U_mu(x) of a site of parity p at [mu][p][.][i >> 1]
+__global__ __launch_bounds__(BS) void links_reorder_kernel(const double2 *src, double2 *dst, Geom g, int64_t V)
+{
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    const int mu = blockIdx.y;
+    if (i >= V) return;
+    int64_t r = i;
+    const int x = (int)(r % g.X);
+    r /= g.X;
+    const int y = (int)(r % g.Y);
+    r /= g.Y;
+    const int z = (int)(r % g.Z);
+    const int t = (int)(r / g.Z);
+    const int par = (x + y + z + t) & 1;
+    const int64_t Vh = V / 2, cb = i >> 1;
+    const double2 *a = src + ((int64_t)mu * V + i) * 9;
+    double2 *b = dst + ((int64_t)(mu * 2 + par) * 9) * Vh + cb;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) b[e * Vh] = a[e];
+}
+
 #define DL_DISPATCH(prec, NAME, ...)                                                                    \
     do {                                                                                                \
         switch (prec) {                                                                                 \
@@ -540,6 +562,14 @@ void k_link_grad(Field se, Field so, Field ae, Field ao, const Geom &g, int nrhs
     ProfScope ps(PROF_TRACE, 4 * field_bytes(P64, g.Vh, nrhs) + 2.0 * 2 * g.Vh * 4 * 9 * 16, s);
     dim3 grid((g.Vh + BS - 1) / BS, 2);
     hipLaunchKernelGGL(link_grad_kernel, grid, dim3(BS), 0, s, se, so, ae, ao, g, nrhs, kappa, grad);
+}
+
+void k_links_reorder(const double *canon, double *dst, const Geom &g, hipStream_t s)
+{
+    const int64_t V = (int64_t)g.X * g.Y * g.Z * g.T;
+    dim3 grid((unsigned)((V + BS - 1) / BS), 4);
+    hipLaunchKernelGGL(links_reorder_kernel, grid, dim3(BS), 0, s, reinterpret_cast<const double2 *>(canon),
+                       reinterpret_cast<double2 *>(dst), g, V);
 }
 
 void k_links_convert(int prec, void *dst, int ne, const double *src64, int64_t Vh, hipStream_t s)

@@ -63,9 +63,21 @@ struct DevBuf {
     }
     ~DevBuf() { release(); }
     void alloc(size_t n);
-    void release();
+    void release() noexcept;
     template <typename T>
     T *as() const { return static_cast<T *>(p); }
+};
+
+// The stream of the entry point running on this thread, for the duration of
+// the call: a device buffer released meanwhile enters the memory cache with an
+// event recorded on it, instead of a device-wide synchronisation.
+struct StreamScope {
+    explicit StreamScope(void *stream);
+    ~StreamScope();
+    StreamScope(const StreamScope &) = delete;
+    StreamScope &operator=(const StreamScope &) = delete;
+    bool prev_known;
+    void *prev;
 };
 
 // nrhs half-spinor fields of one parity in one precision
@@ -296,6 +308,8 @@ void k_adjoint_source(Field dst, int parity, const SourceSpec &src, const Geom &
 // solutions s and adjoint solutions a' (a = gamma5 a'), all FP64 parity fields
 void k_link_grad(Field se, Field so, Field ae, Field ao, const Geom &g, int nrhs, double kappa, double *grad,
                  hipStream_t s);
+// canonical device links [4][V][3][3] complex128 -> [4][2][9][Vh] complex128 (parity split)
+void k_links_reorder(const double *canon, double *dst, const Geom &g, hipStream_t s);
 // links canonical (host-reordered to [4][2][9][Vh] complex128 on the device) -> storage format
 void k_links_convert(int prec, void *dst, int ne, const double *src64, int64_t Vh, hipStream_t s);
 

@@ -186,3 +186,67 @@ def test_bench_defines_every_measurement():
     for f in ("cpu_baseline", "tsm_comparison", "copy_rate", "hop_rate", "dslash_sweep", "differentiation_measurement",
               "batch_measurement", "dilution_study"):
         assert f in defined, f
+
+
+def test_tsm_combine_against_numpy(dl):
+    """dl_tsm_combine (host-only entry, FP64): the estimate mean(LP set) + mean(HP - LP of the HP set)
+    and its variance s2/n + s2/n, with numpy's complex mean and ddof=1 variance as the reference;
+    argument errors return DL_EINVAL."""
+    import numpy as np
+
+    rng = np.random.default_rng(3)
+    n_lp, n_hp, ng, T = 7, 4, 3, 5
+    a = rng.normal(size=(n_lp, ng, T)) + 1j * rng.normal(size=(n_lp, ng, T))
+    b = rng.normal(size=(n_hp, ng, T)) + 1j * rng.normal(size=(n_hp, ng, T))
+    c = b + 0.1 * (rng.normal(size=b.shape) + 1j * rng.normal(size=b.shape))
+    est, var = dl.tsm_estimate(a, b, c)
+    ref_est = a.mean(axis=0) + (b - c).mean(axis=0)
+    ref_var = a.var(axis=0, ddof=1) / n_lp + (b - c).var(axis=0, ddof=1) / n_hp
+    assert est.shape == (ng, T) and var.shape == (ng, T)
+    assert np.max(np.abs(est - ref_est)) <= 1e-14 * np.max(np.abs(ref_est))
+    assert np.max(np.abs(var - ref_var)) <= 1e-14 * np.max(ref_var)
+    lib = dl.load()
+    A = np.zeros((2, 1, 4, 2))
+    E = np.zeros((1, 4, 2))
+    Vv = np.zeros((1, 4))
+    p, e, v = A.ctypes.data, E.ctypes.data, Vv.ctypes.data
+    assert lib.dl_tsm_combine(p, 2, p, p, 2, 1, 4, e, v) == dl.DL_OK
+    assert lib.dl_tsm_combine(p, 1, p, p, 2, 1, 4, e, v) == dl.DL_EINVAL  # variance needs two noises
+    assert lib.dl_tsm_combine(p, 1, p, p, 1, 1, 4, e, None) == dl.DL_OK
+    assert lib.dl_tsm_combine(None, 2, p, p, 2, 1, 4, e, v) == dl.DL_EINVAL
+    assert lib.dl_tsm_combine(p, 2, p, p, 2, 17, 4, e, v) == dl.DL_EINVAL
+    assert lib.dl_tsm_combine(p, 2, p, p, 2, 1, 0, e, v) == dl.DL_EINVAL
+
+
+def test_solve_stats_layout_matches_the_header(dl):
+    """The binding's dl_solve_stats has the header's fields in order (seconds and bytes included)."""
+    import ctypes
+
+    text = open(HEADER).read()
+    body = text[text.index("typedef struct {\n    int32_t status;"):]
+    body = body[:body.index("} dl_solve_stats;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = re.findall(r"\b(int32_t|double)\s+(\w+);", body)
+    assert [n for _, n in names] == [f[0] for f in dl.dl_solve_stats._fields_]
+    assert ctypes.sizeof(dl.dl_solve_stats) == 40
+
+
+def test_binding_does_no_arithmetic_on_results():
+    """The Python binding and the autograd glue only marshal: no numpy reductions or elementwise
+    maths, no complex assembly from real and imaginary parts (complex results are read in place),
+    no .real / .imag / .conj on arrays.  Integer size arithmetic stays allowed."""
+    import ast
+
+    banned_calls = {"mean", "var", "std", "sum", "prod", "dot", "vdot", "einsum", "conj", "conjugate", "real",
+                    "imag", "abs", "sqrt", "exp", "log", "stack", "concatenate", "matmul", "cumsum"}
+    for f in ("__init__.py", "autograd.py"):
+        src = open(os.path.join(ROOT, "paper_1012_5168_amd", f)).read()
+        for node in ast.walk(ast.parse(src)):
+            if isinstance(node, ast.Constant) and isinstance(node.value, complex):
+                raise AssertionError("%s:%d: complex literal" % (f, node.lineno))
+            if isinstance(node, ast.Attribute) and node.attr in ("real", "imag", "conj"):
+                raise AssertionError("%s:%d: .%s" % (f, node.lineno, node.attr))
+            if isinstance(node, ast.Call) and isinstance(node.func, ast.Attribute) and node.func.attr in banned_calls:
+                raise AssertionError("%s:%d: %s()" % (f, node.lineno, node.func.attr))
+            if isinstance(node, ast.BinOp) and isinstance(node.op, (ast.MatMult, ast.Pow)):
+                raise AssertionError("%s:%d: array operator" % (f, node.lineno))

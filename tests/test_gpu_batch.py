@@ -99,3 +99,32 @@ def test_batch_paper_shapes_mixed_precision(dl, dev):
         # both solves meet 1e-10; the loops agree to that order on the Cauchy-Schwarz scale
         scale = 96 * np.prod(synth.WORKLOADS[names[i]]["dims"][:3]) / 8
         assert np.max(np.abs(L[i] - single)) < 1e-7 * scale
+
+
+@pytest.mark.parametrize("own_stream", [False, True])
+def test_capture_failure_leaves_the_stream_usable(dl, dev, monkeypatch, own_stream):
+    """A failure inside a graph capture (forced from the host, after the capture has begun) comes back
+    as an error; the capture is ended and its graph destroyed, so the same stream then runs an eager
+    solve, a graph-replayed solve and ordinary torch work with correct results.  Covers the caller's
+    own stream (captured directly) and the default stream (the library captures on a stream of its
+    own ordered after it)."""
+    dims, U, kappa, G = build(dl, SMALL[:1])[0]
+    gam = [0, 15]
+    src = dl.z2_sources(600, 2)
+    ref, _ = dl.loops(G, kappa, src, gam, dl.solve_params(tol=1e-12, maxiter=2000, poll=2))
+    s = torch.cuda.Stream() if own_stream else torch.cuda.default_stream()
+    with torch.cuda.stream(s):
+        monkeypatch.setenv("DL_FAULT_INJECT", "capture")
+        with pytest.raises(dl.DLError) as e:
+            dl.loops(G, kappa, src, gam, dl.solve_params(tol=1e-12, maxiter=2000, poll=2, use_graph=True))
+        assert "injected" in str(e.value)
+        monkeypatch.delenv("DL_FAULT_INJECT")
+        assert not torch.cuda.is_current_stream_capturing()
+        eager, st = dl.loops(G, kappa, src, gam, dl.solve_params(tol=1e-12, maxiter=2000, poll=2))
+        graph, st2 = dl.loops(G, kappa, src, gam, dl.solve_params(tol=1e-12, maxiter=2000, poll=2, use_graph=True))
+        x = torch.arange(1 << 16, dtype=torch.float64, device=dev)
+        total = float(x.sum())
+    torch.cuda.synchronize()
+    assert all(t[0] == dl.DL_OK for t in st + st2)
+    assert np.array_equal(eager, ref) and np.array_equal(graph, ref)
+    assert total == float((1 << 16) * ((1 << 16) - 1) // 2)

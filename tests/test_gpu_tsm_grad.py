@@ -50,6 +50,9 @@ def test_tsm_parts_against_oracle(dl, dev, lp_prec, tol):
     est, var = dl.tsm_estimate(a, b, c)
     ref_est = oracle.tsm_combine(ref_lp[:n_lp], ref_hp, ref_lp[n_lp:])
     assert np.max(np.abs(est - ref_est)) < max(tol, 1e-9) * np.max(np.abs(ref_lp)) * 2
+    # the library's variance of the estimate on the GPU's own loops, against numpy's
+    ref_var = a.var(axis=0, ddof=1) / n_lp + (b - c).var(axis=0, ddof=1) / n_hp
+    assert np.max(np.abs(var - ref_var)) <= 1e-13 * np.max(ref_var)
     assert all(s[0] == dl.DL_OK for s in st)
 
 
@@ -85,7 +88,7 @@ def test_link_gradient_against_oracle(dl, dev, recon):
     W = rng.standard_normal((2, len(gam), dims[3])) + 1j * rng.standard_normal((2, len(gam), dims[3]))
     prm = dl.solve_params(tol=1e-12, maxiter=2000)
     src = dl.z2_sources(w["noise_seed"], 2, scheme=dl.DL_DIL_SPIN_COLOUR)
-    grad, L, dk, st = dl.loops_link_grad(G, kappa, src, gam, W, prm, with_dkappa=True)
+    grad, L, dk, dfk, st = dl.loops_link_grad(G, kappa, src, gam, W, prm, with_dkappa=True)
     ref = np.zeros_like(grad)
     for n in range(2):
         srcs = [oracle.z2_source(dims, w["noise_seed"], n, 1, d) for d in range(12)]
@@ -95,6 +98,9 @@ def test_link_gradient_against_oracle(dl, dev, recon):
     assert rel(L, refL) < 1e-10
     refd = oracle.loops_dkappa(U, dims, kappa, w["noise_seed"], [0, 1], 1, gam, tol=1e-13)
     assert rel(dk, refd) < 1e-9
+    # the library's contraction of the cotangent with dL/dkappa
+    ref_dfk = float(np.sum((np.conj(W) * refd).real))
+    assert abs(dfk - ref_dfk) < 1e-9 * np.sum(np.abs(W) * np.abs(refd)), (dfk, ref_dfk)
     assert all(s[0] == dl.DL_OK for s in st)
 
 
@@ -114,7 +120,7 @@ def test_link_gradient_directional_difference_on_gpu(dl, dev):
         L, _ = dl.loops(dl.Gauge(lat, Ux, recon=18), kappa, src, gam, prm)
         return np.sum((np.conj(W) * L).real)
 
-    grad, _, _, _ = dl.loops_link_grad(dl.Gauge(lat, U, recon=18), kappa, src, gam, W, prm)
+    grad, _, _, _, _ = dl.loops_link_grad(dl.Gauge(lat, U, recon=18), kappa, src, gam, W, prm)
     for _ in range(2):
         dU = rng.standard_normal(U.shape) + 1j * rng.standard_normal(U.shape)
         h = 1e-5
@@ -142,6 +148,35 @@ def test_autograd_function_gradcheck(dl, dev):
     loss = (L.real ** 2).sum() + L.imag.sum()
     loss.backward()
     assert links.grad is not None and kappa.grad is not None
+
+
+def test_autograd_device_resident_two_forward_calls(dl, dev):
+    """Links and kappa on the GPU: the gauge field is uploaded from device memory, the loops come
+    back on the GPU, and backpropagation through two forward calls (a loss that uses both) gives
+    gradients on the GPU equal to those of the same graph built on host tensors."""
+    from paper_1012_5168_amd.autograd import disconnected_loops
+
+    dims = (2, 2, 2, 4)
+    U = synth.gauge_field(dims, 0.5, seed=232)
+    src1, src2 = dl.z2_sources(43, 1), dl.z2_sources(44, 1, scheme=dl.DL_DIL_SPIN_COLOUR)
+    prm = dl.solve_params(tol=1e-13, maxiter=2000)
+
+    def run(device):
+        links = torch.tensor(np.array(U), dtype=torch.complex128, device=device, requires_grad=True)
+        kappa = torch.tensor(0.12, dtype=torch.float64, device=device, requires_grad=True)
+        L1 = disconnected_loops(kappa, links, dims, src1, [15, 0], prm)
+        L2 = disconnected_loops(kappa, links, dims, src2, [0], prm)
+        assert L1.device == links.device and L2.device == links.device
+        loss = (L1.real ** 2).sum() + (L1.imag * L2.real.sum()).sum()
+        loss.backward()
+        return links.grad, kappa.grad
+
+    g_dev, k_dev = run(dev)
+    g_host, k_host = run("cpu")
+    assert g_dev.device == dev and k_dev.device == dev and k_dev.dtype == torch.float64
+    gd, gh = g_dev.cpu().numpy(), g_host.numpy()
+    assert np.max(np.abs(gd - gh)) <= 1e-12 * np.max(np.abs(gh))
+    assert abs(float(k_dev.cpu()) - float(k_host)) <= 1e-12 * abs(float(k_host))
 
 
 def test_full_size_dkappa_mixed_precision(dl, dev):
@@ -205,7 +240,7 @@ def test_full_size_link_gradient_directional(dl, dev):
         assert all(s[0] == dl.DL_OK for s in st)
         return np.sum((np.conj(W) * L).real)
 
-    grad, _, _, st = dl.loops_link_grad(dl.Gauge(lat, U, recon=18), kappa, src, gam, W, prm)
+    grad, _, _, _, st = dl.loops_link_grad(dl.Gauge(lat, U, recon=18), kappa, src, gam, W, prm)
     dU = rng.standard_normal(U.shape) + 1j * rng.standard_normal(U.shape)
     h = 1e-4
     fd = (F(U + h * dU) - F(U - h * dU)) / (2 * h)
