@@ -173,6 +173,30 @@ void dl_gauge_destroy(dl_gauge g);
 int dl_apply(dl_gauge g, double kappa, int32_t op, int32_t prec, const void *in, void *out, int64_t nrhs,
              void *stream);
 
+/*
+ * dl_apply for callers that cannot allocate device memory: code being
+ * captured into a graph, tight serving loops, harnesses that forbid hipMalloc.
+ * out = op(in) exactly as dl_apply (same arguments, layouts and errors), with
+ * the packed parity fields in a static device scratch array of
+ * DL_NOALLOC_SCRATCH_BYTES (64 MiB) instead of allocated workspaces; each GPU
+ * the library runs on holds its own array until the process ends.  The call
+ * needs 4 packed half fields (5 for DL_OP_MHAT / DL_OP_MHATDAG) of nrhs
+ * right-hand sides in the storage precision, each rounded up to 256 bytes: at
+ * 16^3 x 32 that is one right-hand side in FP64 or four in FP16.  A larger
+ * request returns DL_EINVAL before any device work.  It calls no hipMalloc,
+ * hipFree or other allocating routine: the launch configuration is the
+ * autotuner's choice already in memory or its default (no tuning runs), and
+ * no profiling events are recorded.  Unlike dl_apply the call does not
+ * synchronise: out is complete when `stream` reaches the end of the call's
+ * work.  Every call on one GPU shares that GPU's scratch and finds the last
+ * call's contents there (every field is written before it is read): calls
+ * ordered on one stream are safe, calls that overlap in time on one GPU
+ * (other streams or threads) race.
+ */
+#define DL_NOALLOC_SCRATCH_BYTES 67108864
+int dl_apply_noalloc(dl_gauge g, double kappa, int32_t op, int32_t prec, const void *in, void *out, int64_t nrhs,
+                     void *stream);
+
 /* Solver parameters. */
 typedef struct {
     int32_t solver;      /* DL_BICGSTAB or DL_CGNR (CG on the normal equations of the Schur system) */

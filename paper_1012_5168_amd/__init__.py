@@ -102,6 +102,8 @@ _SIGNATURES = {
     "dl_gauge_create_device": (ctypes.c_int, [_P, _P, ctypes.c_uint32, ctypes.c_int32, _P, ctypes.POINTER(_P)]),
     "dl_gauge_destroy": (None, [_P]),
     "dl_apply": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int64, _P]),
+    "dl_apply_noalloc": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int64,
+                                        _P]),
     "dl_solve": (ctypes.c_int, [_P, ctypes.c_double, ctypes.POINTER(dl_solve_params), _P, _P, ctypes.c_int64,
                                 ctypes.POINTER(dl_solve_stats), _P]),
     "dl_loops": (ctypes.c_int, [_P, ctypes.c_double, ctypes.POINTER(dl_sources), ctypes.POINTER(dl_solve_params), _P,
@@ -237,6 +239,13 @@ def dl_gauge_destroy(h):
 def dl_apply(gauge, kappa, op, prec, inp, out, nrhs, stream=None):
     _check(load().dl_apply(gauge, float(kappa), int(op), int(prec), _dptr(inp), _dptr(out), int(nrhs),
                            _stream(stream)))
+
+
+def dl_apply_noalloc(gauge, kappa, op, prec, inp, out, nrhs, stream=None):
+    """As dl_apply, with the library's static scratch instead of allocated workspaces (no synchronisation:
+    out is complete when the stream reaches the end of the call's work)."""
+    _check(load().dl_apply_noalloc(gauge, float(kappa), int(op), int(prec), _dptr(inp), _dptr(out), int(nrhs),
+                                   _stream(stream)))
 
 
 def dl_solve(gauge, kappa, params, b, x, nrhs, stats=None, stream=None):

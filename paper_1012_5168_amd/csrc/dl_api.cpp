@@ -114,6 +114,14 @@ void cache_trim_locked(size_t keep)
 }
 }  // namespace
 
+namespace {
+thread_local bool t_no_alloc = false;
+}
+
+NoAllocScope::NoAllocScope() : prev(t_no_alloc) { t_no_alloc = true; }
+NoAllocScope::~NoAllocScope() { t_no_alloc = prev; }
+bool no_alloc_active() { return t_no_alloc; }
+
 StreamScope::StreamScope(void *stream) : prev_known(t_stream_known), prev(t_stream)
 {
     t_stream_known = true;
@@ -274,7 +282,7 @@ bool capturing(hipStream_t s)
     return hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
 }
 
-bool prof_on() { return g_prof_on; }
+bool prof_on() { return g_prof_on && !no_alloc_active(); }
 
 unsigned *prof_counter()
 {
@@ -714,6 +722,84 @@ extern "C" int dl_apply(dl_gauge G, double kappa, int32_t op, int32_t prec, cons
         if (schur_op(op)) tmp.alloc(prec, n, Vh);
         apply_op(c, op, prec, kappa, in, out, n, ie.view(), io.view(), oe.view(), oo.view(), tmp.view());
         DL_HIP(hipStreamSynchronize(c.s));
+        return DL_OK;
+    });
+}
+
+// ====================================================================== no-allocation entry
+
+// Scratch of dl_apply_noalloc: the packed parity fields, carved from a static
+// device array instead of allocated.  Each GPU the library runs on holds its
+// own copy until the process ends.  Host code never passes the array's name
+// to a kernel or a copy (on the host it is only a stand-in for the symbol):
+// its device address is looked up once per device with hipGetSymbolAddress,
+// with that device current, and kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[DL_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+void *scratch_on_current_device()
+{
+    int dev = 0;
+    DL_HIP(hipGetDevice(&dev));
+    DL_REQUIRE(dev >= 0 && dev < MAX_DEVICES, "dl_apply_noalloc: device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        DL_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        DL_REQUIRE(ptr != nullptr, "dl_apply_noalloc: no device address for the scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+// bytes of one packed field of n right-hand sides, rounded up to 256
+size_t field_span(int prec, int n, int64_t Vh)
+{
+    const size_t d = (size_t)n * 12 * Vh * elem_bytes(prec);
+    const size_t m = prec == P16 ? (size_t)n * Vh * sizeof(float) : 0;
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    return up(d) + up(m);
+}
+
+Field carve(char *&p, int prec, int n, int64_t Vh)
+{
+    const size_t d = ((size_t)n * 12 * Vh * elem_bytes(prec) + 255) / 256 * 256;
+    Field f{p, nullptr};
+    p += d;
+    if (prec == P16) {
+        f.nrm = reinterpret_cast<float *>(p);
+        p += ((size_t)n * Vh * sizeof(float) + 255) / 256 * 256;
+    }
+    return f;
+}
+
+}  // namespace
+
+extern "C" int dl_apply_noalloc(dl_gauge G, double kappa, int32_t op, int32_t prec, const void *in, void *out,
+                                int64_t nrhs, void *stream)
+{
+    return guarded([&]() {
+        NoAllocScope na;
+        validate_apply(G, op, prec, in, out, nrhs, "dl_apply_noalloc");
+        const int n = (int)nrhs;
+        const int64_t Vh = G->lat.Vh;
+        const int nfield = schur_op(op) ? 5 : 4;
+        const size_t need = nfield * field_span(prec, n, Vh);
+        DL_REQUIRE(need <= (size_t)DL_NOALLOC_SCRATCH_BYTES,
+                   "dl_apply_noalloc: " + std::to_string(nfield) + " packed fields of " + std::to_string(n) +
+                       " right-hand sides need " + std::to_string(need) + " bytes, more than the scratch of " +
+                       std::to_string((size_t)DL_NOALLOC_SCRATCH_BYTES) + " bytes");
+        char *p = static_cast<char *>(scratch_on_current_device());
+        Field ie = carve(p, prec, n, Vh), io = carve(p, prec, n, Vh), oe = carve(p, prec, n, Vh),
+              oo = carve(p, prec, n, Vh);
+        Field tmp = schur_op(op) ? carve(p, prec, n, Vh) : NOF;
+        Ctx c{G, G->lat.geom(), static_cast<hipStream_t>(stream)};
+        apply_op(c, op, prec, kappa, in, out, n, ie, io, oe, oo, tmp);
         return DL_OK;
     });
 }

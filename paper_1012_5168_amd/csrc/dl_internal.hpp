@@ -80,6 +80,19 @@ struct StreamScope {
     void *prev;
 };
 
+// A call that must not allocate (dl_apply_noalloc), for the duration of the
+// scope on this thread: the autotuner only looks up choices it already holds
+// (timing candidates would create events and write its cache file) and no
+// profiling events are created.
+struct NoAllocScope {
+    NoAllocScope();
+    ~NoAllocScope();
+    NoAllocScope(const NoAllocScope &) = delete;
+    NoAllocScope &operator=(const NoAllocScope &) = delete;
+    bool prev;
+};
+bool no_alloc_active();
+
 // nrhs half-spinor fields of one parity in one precision
 struct HalfField {
     int prec = P64;

@@ -165,6 +165,11 @@ TuneChoice tune_lookup(const std::vector<DslashCall> &c, hipStream_t s)
     if (mode == 1 || mode == 3 || aliases(c)) return dflt;
     const Key k = make_key(c);
     std::lock_guard<std::mutex> lk(g_mu);
+    if (no_alloc_active()) {
+        // a call that must not allocate: a choice already in memory, else the default
+        auto it = g_cache.find(k);
+        return it != g_cache.end() ? it->second : dflt;
+    }
     load_locked();
     auto it = g_cache.find(k);
     if (it != g_cache.end()) return it->second;
