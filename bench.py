@@ -9,11 +9,14 @@ traces L_1(t), L_gamma5(t).  The gauge field and all workspaces are resident
 on the GPU before the timed region; the sources are generated on the GPU
 inside it.
 
-The JSON line reports the hopping kernel's achieved bandwidth (algorithmic
-bytes of every launch, each operand moved once, over the summed event-timed
-kernel durations on the library's stream) as `value` and against the HBM
-roofline, the time per step / per converged solve, and the CPU oracle timed
-on a bounded sample of the same workload.
+The JSON line reports as `value` the achieved bandwidth of the plain half
+dslash (the stencil without a fused epilogue: algorithmic bytes of every such
+launch, each operand moved once, over their summed event-timed durations on
+the library's stream), the same figure against the HBM roofline, the rate of
+all hopping launches, the time per step / per converged solve, the truncated
+solver method's time to equal variance with its measured per-loop error
+against the FP64 oracle, and the CPU oracle timed on a bounded sample of the
+same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -102,6 +105,29 @@ def cpu_baseline(w, n_apply=10, n_solve=3):
     }
 
 
+def lp_error_vs_oracle(lp_loops, gammas):
+    """Error of the low-precision loops of the first noises of the LP set against the FP64 run of the
+    same truncated algorithm by the oracle, stored by tests/golden/make_tsm_lp_reference.py (no
+    oracle code runs here): per Gamma, the largest over noises and t of |dL| / (sum_{x in t}
+    |eta| |s|) (Cauchy-Schwarz-normalised) and of |dL(t)| / max_t |L(t)| (raw)."""
+    import numpy as np
+
+    path = os.path.join(ROOT, "tests", "golden", "tsm_lp_fp64_16x16x16x32.json")
+    with open(path) as f:
+        ref = json.load(f)
+    out = {"noises": len(ref["noises"]), "reference": "oracle FP64, same 25 CGNR iterations"}
+    for k, g in enumerate(ref["gammas"]):
+        gi = gammas.index(g)
+        cs_max = raw_max = 0.0
+        for r in ref["noises"]:
+            L = np.array(r["loops_re"][k]) + 1j * np.array(r["loops_im"][k])
+            d = np.abs(lp_loops[r["noise"]][gi] - L)
+            cs_max = max(cs_max, float(np.max(d / np.array(r["cs_scale"]))))
+            raw_max = max(raw_max, float(np.max(d) / np.max(np.abs(L))))
+        out["gamma%d" % g] = {"cs_normalised_max": cs_max, "raw_max": raw_max}
+    return out
+
+
 def tsm_comparison(dl, G, w, L_plain, ms_plain, lp_prec=None):
     """Time per loop at fixed statistical error: the truncated solver method (400 low-precision
     truncated solves in FP16 storage (or lp_prec) / FP32 arithmetic, 25 CGNR iterations, plus 16
@@ -127,7 +153,8 @@ def tsm_comparison(dl, G, w, L_plain, ms_plain, lp_prec=None):
     est, var_t = dl.tsm_estimate(a, b, c)
     var_p = np.var(L_plain, axis=0, ddof=1) / len(L_plain)
     out = {"ms_tsm": round(ms_tsm, 2), "ms_plain": round(ms_plain, 2), "n_lp": n_lp, "n_hp": n_hp,
-           "hp_converged": all(x[0] == dl.DL_OK for x in st[(n_lp + n_hp):])}
+           "hp_converged": all(x[0] == dl.DL_OK for x in st[(n_lp + n_hp):]),
+           "lp_loop_error_vs_fp64_oracle": lp_error_vs_oracle(a, gam)}
     # bootstrap over noises (LP set, HP set and the plain estimate's noises resampled independently)
     rng = np.random.default_rng(12345)
     nboot = 400
@@ -416,6 +443,8 @@ def main():
     dl.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    # this process owns the GPU: keep the workspaces of every workload in the library's memory cache
+    dl.dl_cache_set_limit(256 << 30)
     dims, kappa = w["dims"], w["kappa"]
     U = synth.gauge_field(dims, w["eps"], w["gauge_seed"])
     lat = dl.Lattice(dims, 1)
@@ -476,11 +505,18 @@ def main():
     assert all(s[0] == dl.DL_OK for s in st), "a solve did not converge"
 
     ms_step = elapsed / args.steps * 1e3
+    # one more step without the per-launch profiling events, for the truncated solver method's time
+    # ratio (its calls run unprofiled too)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step()
+    torch.cuda.synchronize()
+    ms_step_unprofiled = (time.perf_counter() - t0) * 1e3
     dslash_gbs = by_d / (ms_d * 1e-3) / 1e9
     plain_gbs = by_p / (ms_p * 1e-3) / 1e9
     out = {
         "metric": "dslash HBM GB/s; time per loop at fixed stat. error vs plain FP64 solver",
-        "value": round(dslash_gbs, 1),
+        "value": round(plain_gbs, 1),
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -498,6 +534,7 @@ def main():
             "lattice": list(dims),
             "rhs": nrhs,
         },
+        "ms_per_step_unprofiled": round(ms_step_unprofiled, 2),
         "ms_per_converged_solve": round(ms_step / nrhs, 4),
         "mean_iterations": float(np.mean(iters)),
         "kernel_ms_per_step": {
@@ -526,9 +563,9 @@ def main():
         },
     }
     if not args.no_tsm:
-        out["tsm"] = tsm_comparison(dl, G, w, L, ms_step)
+        out["tsm"] = tsm_comparison(dl, G, w, L, ms_step_unprofiled)
         # the same split with the low-precision solves in BF16 storage (coarser mantissa, no scales)
-        out["tsm_bf16_lp"] = tsm_comparison(dl, G, w, L, ms_step, lp_prec=dl.DL_BF16)
+        out["tsm_bf16_lp"] = tsm_comparison(dl, G, w, L, ms_step_unprofiled, lp_prec=dl.DL_BF16)
         # the same 288 solves with FP32 iterations and FP64 reliable updates to the same 1e-10
         pm = dl.solve_params(prec=dl.DL_F32, tol=1e-10, maxiter=2000)
         dl.loops(G, kappa, src, gam, pm)

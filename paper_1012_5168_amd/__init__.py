@@ -389,6 +389,15 @@ def dl_cache_release():
     _check(load().dl_cache_release())
 
 
+def dl_cache_set_limit(nbytes: int):
+    """Cap the bytes the library's device memory cache may hold (0 turns caching off)."""
+    _check(load().dl_cache_set_limit(int(nbytes)))
+
+
+def dl_cache_bytes() -> int:
+    return int(load().dl_cache_bytes())
+
+
 def dl_profile_config(kind: int):
     """(kernel, right-hand sides or wavefronts, sites per workgroup, grid cap or region blocks) of the
     last profiled hopping launch of that kind; all -1 if none."""
