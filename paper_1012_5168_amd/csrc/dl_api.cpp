@@ -1860,6 +1860,12 @@ extern "C" int dl_smear(dl_gauge G, double alpha, int32_t iters, const void *in,
         Ctx c{G, G->lat.geom(), static_cast<hipStream_t>(stream)};
         const int n = (int)nrhs;
         const int64_t Vh = G->lat.Vh;
+        if (iters == 0) {
+            // S = 1: the output is the input, bit for bit
+            DL_HIP(hipMemcpyAsync(out, in, (size_t)n * G->lat.V * 24 * sizeof(double), hipMemcpyDeviceToDevice, c.s));
+            DL_HIP(hipStreamSynchronize(c.s));
+            return DL_OK;
+        }
         HalfField ae, ao, be, bo;
         ae.alloc(P64, n, Vh);
         ao.alloc(P64, n, Vh);

@@ -4,11 +4,12 @@
 //
 // Device layouts (private to the library):
 //   half-spinor field of one parity, one right-hand side: 12 complex
-//   components (spin-major, then colour) stored structure-of-arrays in
-//   16-byte vectors of VEC consecutive components (VEC = 1 for FP64, 2 for
-//   FP32, 4 for FP16 / BF16): component e of checkerboard site cb at element
-//   [(e / VEC) * Vh + cb] * VEC + e % VEC, so one lane's 16-byte load brings
-//   VEC components and a wavefront's load covers 64 consecutive sites; nrhs
+//   components (spin-major, then colour) in the stored spin basis (see
+//   to_internal below), structure-of-arrays in 16-byte vectors of VEC
+//   components (VEC = 1 for FP64, 2 for FP32, 4 for FP16 / BF16): vector j of
+//   checkerboard site cb at vector index j * Vh + cb, holding the components
+//   comp_of<VEC>(j, 0 .. VEC-1), so one lane's 16-byte load brings VEC
+//   components and a wavefront's load covers 64 consecutive sites; nrhs
 //   fields follow each other with stride 12 * Vh elements.  FP16 fields carry
 //   an extra FP32 scale per site ([rhs * Vh + cb]) and store entries divided
 //   by it.
@@ -87,9 +88,6 @@ struct Fmt<double> {
         return {v.x, v.y};
     }
     __device__ static __forceinline__ void st(E *p, int64_t i, cx<double> v) { p[i] = make_double2(v.re, v.im); }
-    // the k-th 16-byte vector of VEC components
-    __device__ static __forceinline__ void ldv(const E *p, int64_t k, cx<double> v[1]) { v[0] = ld(p, k); }
-    __device__ static __forceinline__ void stv(E *p, int64_t k, const cx<double> v[1]) { st(p, k, v[0]); }
     // the components of one 16-byte vector read as raw words
     __device__ static __forceinline__ void unpack(const uint4 &q, cx<double> v[1])
     {
@@ -117,16 +115,6 @@ struct Fmt<float> {
         return {v.x, v.y};
     }
     __device__ static __forceinline__ void st(E *p, int64_t i, cx<float> v) { p[i] = make_float2(v.re, v.im); }
-    __device__ static __forceinline__ void ldv(const E *p, int64_t k, cx<float> v[2])
-    {
-        const float4 q = reinterpret_cast<const float4 *>(p)[k];
-        v[0] = {q.x, q.y};
-        v[1] = {q.z, q.w};
-    }
-    __device__ static __forceinline__ void stv(E *p, int64_t k, const cx<float> v[2])
-    {
-        reinterpret_cast<float4 *>(p)[k] = make_float4(v[0].re, v[0].im, v[1].re, v[1].im);
-    }
     __device__ static __forceinline__ void unpack(const uint4 &q, cx<float> v[2])
     {
         float4 f;
@@ -157,11 +145,6 @@ __device__ __forceinline__ void unpack16(const uint4 &q, cx<float> v[4], CVT cvt
     }
 }
 template <typename H2, typename CVT>
-__device__ __forceinline__ void ldv16(const H2 *p, int64_t k, cx<float> v[4], CVT cvt)
-{
-    unpack16<H2>(reinterpret_cast<const uint4 *>(p)[k], v, cvt);
-}
-template <typename H2, typename CVT>
 __device__ __forceinline__ uint4 pack16(const cx<float> v[4], CVT cvt)
 {
     unsigned w[4];
@@ -172,10 +155,18 @@ __device__ __forceinline__ uint4 pack16(const cx<float> v[4], CVT cvt)
     }
     return make_uint4(w[0], w[1], w[2], w[3]);
 }
+// two 16-bit complex numbers in 8 bytes
 template <typename H2, typename CVT>
-__device__ __forceinline__ void stv16(H2 *p, int64_t k, const cx<float> v[4], CVT cvt)
+__device__ __forceinline__ void unpack16x2(const uint2 &q, cx<float> v[2], CVT cvt)
 {
-    reinterpret_cast<uint4 *>(p)[k] = pack16<H2>(v, cvt);
+    const unsigned w[2] = {q.x, q.y};
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        H2 h;
+        __builtin_memcpy(&h, &w[i], 4);
+        const float2 f = cvt(h);
+        v[i] = {f.x, f.y};
+    }
 }
 template <>
 struct Fmt<__half> {
@@ -192,17 +183,13 @@ struct Fmt<__half> {
         p[i] = __float22half2_rn(make_float2(v.re, v.im));
     }
     static constexpr int VEC = 4;
-    __device__ static __forceinline__ void ldv(const E *p, int64_t k, cx<float> v[4])
-    {
-        ldv16(p, k, v, [](E h) { return __half22float2(h); });
-    }
-    __device__ static __forceinline__ void stv(E *p, int64_t k, const cx<float> v[4])
-    {
-        stv16(p, k, v, [](float2 f) { return __float22half2_rn(f); });
-    }
     __device__ static __forceinline__ void unpack(const uint4 &q, cx<float> v[4])
     {
         unpack16<E>(q, v, [](E h) { return __half22float2(h); });
+    }
+    __device__ static __forceinline__ void unpack2(const uint2 &q, cx<float> v[2])
+    {
+        unpack16x2<E>(q, v, [](E h) { return __half22float2(h); });
     }
     __device__ static __forceinline__ uint4 pack(const cx<float> v[4])
     {
@@ -224,17 +211,13 @@ struct Fmt<__hip_bfloat16> {
         p[i] = __float22bfloat162_rn(make_float2(v.re, v.im));
     }
     static constexpr int VEC = 4;
-    __device__ static __forceinline__ void ldv(const E *p, int64_t k, cx<float> v[4])
-    {
-        ldv16(p, k, v, [](E h) { return __bfloat1622float2(h); });
-    }
-    __device__ static __forceinline__ void stv(E *p, int64_t k, const cx<float> v[4])
-    {
-        stv16(p, k, v, [](float2 f) { return __float22bfloat162_rn(f); });
-    }
     __device__ static __forceinline__ void unpack(const uint4 &q, cx<float> v[4])
     {
         unpack16<E>(q, v, [](E h) { return __bfloat1622float2(h); });
+    }
+    __device__ static __forceinline__ void unpack2(const uint2 &q, cx<float> v[2])
+    {
+        unpack16x2<E>(q, v, [](E h) { return __bfloat1622float2(h); });
     }
     __device__ static __forceinline__ uint4 pack(const cx<float> v[4])
     {
@@ -244,9 +227,60 @@ struct Fmt<__hip_bfloat16> {
 
 // A set of nrhs half-spinor fields of one parity.
 struct Field {
-    void *d;       // [nrhs][12][Vh] packed complex of the storage type
+    void *d;       // [nrhs][12/VEC][Vh] 16-byte vectors of the storage type
     float *nrm;    // [nrhs][Vh] per-site scale (FP16 only, else null)
 };
+
+// Spin basis of the stored fields.  Every spinor field is stored in the basis
+// psi' = T psi, T = [[1, 1], [1, -1]] acting on the (upper, lower) spin pairs
+// of the chiral basis.  T / sqrt 2 is real, symmetric and its own inverse,
+// and the scale cancels in the operator: in this basis gamma_4 = diag(1, 1,
+// -1, -1), so a temporal projector (1 +- gamma_4) keeps one spin pair and a
+// temporal hop reads half of its neighbour's spinor, and gamma_k = [[0,
+// i sigma_k], [-i sigma_k, 0]] (the chiral A_k = -i sigma_k with its sign
+// flipped).  Inner products and norms scale by 2, so relative residuals and
+// the Krylov coefficients are unchanged.  Fields cross to and from the
+// canonical basis through to_internal / to_canonical; the factor 1/2 is
+// exact, so a complex Z2 or unit source survives the round trip bit for bit.
+template <typename R>
+__device__ __forceinline__ void to_internal(cx<R> v[12])
+{
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const cx<R> u = v[k], d = v[6 + k];
+        v[k] = u + d;
+        v[6 + k] = u - d;
+    }
+}
+template <typename R>
+__device__ __forceinline__ void to_canonical(cx<R> v[12])
+{
+    const R h = R(0.5);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const cx<R> u = v[k], d = v[6 + k];
+        v[k] = h * (u + d);
+        v[6 + k] = h * (u - d);
+    }
+}
+
+// The component (3 spin + colour) held by entry q of 16-byte vector j of a
+// stored spinor with VEC entries per vector.  VEC = 1 and 2 keep the
+// components in order.  The 16-bit formats (VEC = 4) hold {0, 1, 2, 3},
+// {6, 7, 8, 9} and {4, 5, 10, 11}: the upper spin pair (0-5) is then vector 0
+// and the low 8 bytes of vector 2, the lower pair (6-11) vector 1 and the high
+// 8 bytes of vector 2, so either pair loads as 24 contiguous-per-lane bytes.
+template <int V>
+__host__ __device__ constexpr int comp_of(int j, int q)
+{
+    return V < 4 ? j * V + q : (j == 0 ? q : j == 1 ? 6 + q : (q < 2 ? 4 + q : 8 + q));
+}
+
+template <typename S>
+__device__ __forceinline__ const char *spinor_base(const Field &f, int64_t Vh, int rhs)
+{
+    return static_cast<const char *>(f.d) + (int64_t)rhs * 12 * Vh * (int64_t)sizeof(typename Fmt<S>::E);
+}
 
 // NT: non-temporal loads (data the kernel reads once)
 template <typename S, bool NT = false>
@@ -255,24 +289,52 @@ __device__ __forceinline__ void load_spinor(const Field &f, int64_t Vh, int rhs,
 {
     using F = Fmt<S>;
     using R = typename F::R;
+    using U4 = unsigned __attribute__((ext_vector_type(4)));
     constexpr int V = F::VEC;
-    const typename F::E *p = static_cast<const typename F::E *>(f.d) + (int64_t)rhs * 12 * Vh;
+    const uint4 *p = reinterpret_cast<const uint4 *>(spinor_base<S>(f, Vh, rhs));
 #pragma unroll
     for (int j = 0; j < 12 / V; ++j) {
+        uint4 q;
         if constexpr (NT) {
-            using U4 = unsigned __attribute__((ext_vector_type(4)));
             const U4 raw = __builtin_nontemporal_load(reinterpret_cast<const U4 *>(p) + ((int64_t)j * Vh + cb));
-            uint4 q;
             __builtin_memcpy(&q, &raw, 16);
-            F::unpack(q, v + j * V);
         } else {
-            F::ldv(p, (int64_t)j * Vh + cb, v + j * V);
+            q = p[(int64_t)j * Vh + cb];
         }
+        cx<R> t[V];
+        F::unpack(q, t);
+#pragma unroll
+        for (int k = 0; k < V; ++k) v[comp_of<V>(j, k)] = t[k];
     }
     if constexpr (F::scaled) {
         R s = NT ? __builtin_nontemporal_load(f.nrm + (int64_t)rhs * Vh + cb) : f.nrm[(int64_t)rhs * Vh + cb];
 #pragma unroll
         for (int e = 0; e < 12; ++e) v[e] = s * v[e];
+    }
+}
+
+// One spin pair of a stored spinor into v[0..5]: H = 0 the upper pair
+// (components 0-5), H = 1 the lower pair (6-11).
+template <typename S, int H>
+__device__ __forceinline__ void load_half(const Field &f, int64_t Vh, int rhs, int64_t cb,
+                                          cx<typename Fmt<S>::R> v[6])
+{
+    using F = Fmt<S>;
+    using R = typename F::R;
+    constexpr int V = F::VEC;
+    const char *base = spinor_base<S>(f, Vh, rhs);
+    const uint4 *p = reinterpret_cast<const uint4 *>(base);
+    if constexpr (V == 4) {
+        F::unpack(p[(int64_t)H * Vh + cb], v);
+        F::unpack2(reinterpret_cast<const uint2 *>(base)[(2 * Vh + cb) * 2 + H], v + 4);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 6 / V; ++j) F::unpack(p[(int64_t)(H * 6 / V + j) * Vh + cb], v + j * V);
+    }
+    if constexpr (F::scaled) {
+        const R s = f.nrm[(int64_t)rhs * Vh + cb];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) v[e] = s * v[e];
     }
 }
 
@@ -291,6 +353,14 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t spinor_rsrc(const Field &f, in
     return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, bytes, 0x00020000);
 }
 
+template <typename S>
+__device__ __forceinline__ float load_scale_rsrc(const Field &f, int Vh, int rhs, int cb)
+{
+    const __amdgpu_buffer_rsrc_t rn =
+        __builtin_amdgcn_make_buffer_rsrc(f.nrm + (int64_t)rhs * Vh, (short)0, Vh * 4, 0x00020000);
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rn, cb * 4, 0, 0));
+}
+
 // AUX: the loads' cache policy (0 = default; 2 = non-temporal, for data read
 // once, so that it does not displace reused lines in L2).
 template <typename S, int AUX = 0>
@@ -306,14 +376,49 @@ __device__ __forceinline__ void load_spinor_rsrc(__amdgpu_buffer_rsrc_t rs, cons
         const auto raw = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, j * Vh * 16, AUX);
         uint4 q;
         __builtin_memcpy(&q, &raw, 16);
-        F::unpack(q, v + j * V);
+        cx<R> t[V];
+        F::unpack(q, t);
+#pragma unroll
+        for (int k = 0; k < V; ++k) v[comp_of<V>(j, k)] = t[k];
     }
     if constexpr (F::scaled) {
-        const __amdgpu_buffer_rsrc_t rn =
-            __builtin_amdgcn_make_buffer_rsrc(f.nrm + (int64_t)rhs * Vh, (short)0, Vh * 4, 0x00020000);
-        R s = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rn, cb * 4, 0, 0));
+        const R s = load_scale_rsrc<S>(f, Vh, rhs, cb);
 #pragma unroll
         for (int e = 0; e < 12; ++e) v[e] = s * v[e];
+    }
+}
+
+// One spin pair (H as load_half) through a buffer resource.
+template <typename S, int H, int AUX = 0>
+__device__ __forceinline__ void load_half_rsrc(__amdgpu_buffer_rsrc_t rs, const Field &f, int Vh, int rhs, int cb,
+                                               cx<typename Fmt<S>::R> v[6])
+{
+    using F = Fmt<S>;
+    using R = typename F::R;
+    constexpr int V = F::VEC;
+    const int voff = cb * 16;
+    if constexpr (V == 4) {
+        const auto raw = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, H * Vh * 16, AUX);
+        uint4 q;
+        __builtin_memcpy(&q, &raw, 16);
+        F::unpack(q, v);
+        const auto raw2 = __builtin_amdgcn_raw_buffer_load_b64(rs, voff + 8 * H, 2 * Vh * 16, AUX);
+        uint2 q2;
+        __builtin_memcpy(&q2, &raw2, 8);
+        F::unpack2(q2, v + 4);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 6 / V; ++j) {
+            const auto raw = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, (H * 6 / V + j) * Vh * 16, AUX);
+            uint4 q;
+            __builtin_memcpy(&q, &raw, 16);
+            F::unpack(q, v + j * V);
+        }
+    }
+    if constexpr (F::scaled) {
+        const R s = load_scale_rsrc<S>(f, Vh, rhs, cb);
+#pragma unroll
+        for (int e = 0; e < 6; ++e) v[e] = s * v[e];
     }
 }
 
@@ -327,15 +432,19 @@ __device__ __forceinline__ void store_spinor(const Field &f, int64_t Vh, int rhs
     using R = typename F::R;
     using U4 = unsigned __attribute__((ext_vector_type(4)));
     constexpr int V = F::VEC;
-    typename F::E *p = static_cast<typename F::E *>(f.d) + (int64_t)rhs * 12 * Vh;
-    auto put = [&](int64_t k, const cx<R> *w) {
+    uint4 *p = reinterpret_cast<uint4 *>(const_cast<char *>(spinor_base<S>(f, Vh, rhs)));
+    auto put = [&](int j, const cx<R> *w) {
+        cx<R> t[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) t[k] = w[comp_of<V>(j, k)];
+        const uint4 q = F::pack(t);
+        const int64_t k = (int64_t)j * Vh + cb;
         if constexpr (NT) {
-            const uint4 q = F::pack(w);
             U4 raw;
             __builtin_memcpy(&raw, &q, 16);
             __builtin_nontemporal_store(raw, reinterpret_cast<U4 *>(p) + k);
         } else {
-            F::stv(p, k, w);
+            p[k] = q;
         }
     };
     if constexpr (F::scaled) {
@@ -351,10 +460,10 @@ __device__ __forceinline__ void store_spinor(const Field &f, int64_t Vh, int rhs
 #pragma unroll
         for (int e = 0; e < 12; ++e) w[e] = inv * v[e];
 #pragma unroll
-        for (int j = 0; j < 12 / V; ++j) put((int64_t)j * Vh + cb, w + j * V);
+        for (int j = 0; j < 12 / V; ++j) put(j, w);
     } else {
 #pragma unroll
-        for (int j = 0; j < 12 / V; ++j) put((int64_t)j * Vh + cb, v + j * V);
+        for (int j = 0; j < 12 / V; ++j) put(j, v);
     }
 }
 

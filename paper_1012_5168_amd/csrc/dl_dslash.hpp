@@ -3,11 +3,16 @@
 //
 // (D psi)(x) = sum_mu (1 - g_mu) b U_mu(x) psi(x+mu) + (1 + g_mu) b U_mu(x-mu)^+ psi(x-mu)
 // (D^+ flips both projector signs).  Each neighbour spinor is projected to a
-// half spinor (two spin components) before the colour multiply, using the
-// block form g_mu = [[0, A_mu], [A_mu^+, 0]] of the chiral basis
-// (A_k = -i sigma_k, A_4 = 1):
-//     (1 + s g_mu) psi = [h ; s A_mu^+ h],   h = psi_up + s A_mu psi_down,
-// so a hop costs two SU(3) matrix-vector products instead of four.
+// half spinor (two spin components) before the colour multiply, so a hop costs
+// two SU(3) matrix-vector products instead of four.  The fields are stored in
+// the spin basis of dl_common.hpp (T = [[1, 1], [1, -1]] applied to the chiral
+// basis).  There the spatial gammas keep the block form g_k = [[0, A_k],
+// [A_k^+, 0]] with A_k = +i sigma_k (the chiral -i sigma_k with its sign
+// flipped):
+//     (1 + s g_k) psi = [h ; s A_k^+ h],   h = psi_up + s A_k psi_down,
+// and g_4 = diag(1, 1, -1, -1): (1 + g_4) psi = [2 psi_up ; 0] and
+// (1 - g_4) psi = [0 ; 2 psi_down], so a temporal hop reads one spin pair of
+// its neighbour, half the bytes of a spatial one.
 #pragma once
 
 #include "dl_internal.hpp"
@@ -27,7 +32,9 @@ struct DKArgs {
     unsigned *live_count;
 };
 
-// h = psi_up + s A_mu psi_down (two spin components x three colours)
+// h = psi_up + s A_mu psi_down (two spin components x three colours) with the
+// chiral A_mu (A_k = -i sigma_k, A_4 = 1); the stored basis uses it with s
+// negated for the spatial directions
 template <typename R, int MU, int SG>
 __device__ __forceinline__ void project(const cx<R> p[12], cx<R> h[6])
 {
@@ -75,18 +82,10 @@ __device__ __forceinline__ void reconstruct(cx<R> acc[12], const cx<R> g[6])
     }
 }
 
-// One hop on a loaded neighbour spinor: project, colour-multiply by U
-// (forward) or U^+ (backward), reconstruct into the accumulator.
-template <typename R, int MU, int SG, bool FWD>
-__device__ __forceinline__ void hop_mul(const cx<R> u[9], const cx<R> psi[12], R bsign, cx<R> acc[12])
+// gg = U h (forward) or U^+ h (backward) for both spin rows of a half spinor
+template <typename R, bool FWD>
+__device__ __forceinline__ void colour_mul(const cx<R> u[9], const cx<R> h[6], cx<R> gg[6])
 {
-    cx<R> h[6];
-    project<R, MU, SG>(psi, h);
-    if constexpr (MU == 3) {
-#pragma unroll
-        for (int e = 0; e < 6; ++e) h[e] = bsign * h[e];
-    }
-    cx<R> gg[6];
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
@@ -101,7 +100,37 @@ __device__ __forceinline__ void hop_mul(const cx<R> u[9], const cx<R> psi[12], R
             }
             gg[3 * sp + i] = t;
         }
-    reconstruct<R, MU, SG>(acc, gg);
+}
+
+// One spatial hop (MU < 3) on a loaded neighbour spinor in the stored basis:
+// project with the projector (1 + SG g_MU), colour-multiply by U (forward)
+// or U^+ (backward), reconstruct into the accumulator.
+template <typename R, int MU, int SG, bool FWD>
+__device__ __forceinline__ void hop_mul(const cx<R> u[9], const cx<R> psi[12], cx<R> acc[12])
+{
+    static_assert(MU < 3, "temporal hops take one spin pair (hop_mul_t)");
+    cx<R> h[6], gg[6];
+    project<R, MU, -SG>(psi, h);
+    colour_mul<R, FWD>(u, h, gg);
+    reconstruct<R, MU, -SG>(acc, gg);
+}
+
+// The spin pair a temporal projector (1 + SG g_4) keeps: 0 = upper, 1 = lower.
+template <int SG>
+constexpr int t_half() { return SG > 0 ? 0 : 1; }
+
+// One temporal hop: `half` is the spin pair t_half<SG>() of the neighbour and
+// coef = 2 b (the projector's 2 times the time-boundary sign).
+template <typename R, int SG, bool FWD>
+__device__ __forceinline__ void hop_mul_t(const cx<R> u[9], const cx<R> half[6], R coef, cx<R> acc[12])
+{
+    cx<R> h[6], gg[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) h[e] = coef * half[e];
+    colour_mul<R, FWD>(u, h, gg);
+    constexpr int o = 6 * t_half<SG>();
+#pragma unroll
+    for (int e = 0; e < 6; ++e) acc[o + e] = acc[o + e] + gg[e];
 }
 
 // Pin the accumulators: this forces a hop's arithmetic to finish before the
@@ -126,9 +155,15 @@ __device__ __forceinline__ void hop(const DKArgs &a, int64_t nb, int lpar, int64
     load_link<S, NE>(a.links, Vh, MU, lpar, lcb, u);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        cx<R> psi[12];
-        load_spinor<S>(a.in, Vh, rhs[r], nb, psi);
-        hop_mul<R, MU, SG, FWD>(u, psi, bsign, acc[r]);
+        if constexpr (MU == 3) {
+            cx<R> half[6];
+            load_half<S, t_half<SG>()>(a.in, Vh, rhs[r], nb, half);
+            hop_mul_t<R, SG, FWD>(u, half, R(2) * bsign, acc[r]);
+        } else {
+            cx<R> psi[12];
+            load_spinor<S>(a.in, Vh, rhs[r], nb, psi);
+            hop_mul<R, MU, SG, FWD>(u, psi, acc[r]);
+        }
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r) pin_acc<R>(acc[r]);
@@ -401,7 +436,6 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
         }
         __syncthreads();
 
-        const R one = R(1);
         const R bf = (g.tap && s.t + 1 == g.T) ? R(-1) : R(1);
         const R bb = (g.tap && s.t == 0) ? R(-1) : R(1);
         unsigned nlive = 0;
@@ -434,17 +468,25 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
                         u[7] = conj(u[2] * u[3] - u[0] * u[5]);
                         u[8] = conj(u[0] * u[4] - u[1] * u[3]);
                     }
-                    cx<R> psi[12];
-                    load_spinor_rsrc<S>(rin, a.in, g.Vh, r, nb[d], psi);
-                    switch (d) {
-                    case 0: hop_mul<R, 0, SF, true>(u, psi, one, acc); break;
-                    case 1: hop_mul<R, 0, SB, false>(u, psi, one, acc); break;
-                    case 2: hop_mul<R, 1, SF, true>(u, psi, one, acc); break;
-                    case 3: hop_mul<R, 1, SB, false>(u, psi, one, acc); break;
-                    case 4: hop_mul<R, 2, SF, true>(u, psi, one, acc); break;
-                    case 5: hop_mul<R, 2, SB, false>(u, psi, one, acc); break;
-                    case 6: hop_mul<R, 3, SF, true>(u, psi, bf, acc); break;
-                    default: hop_mul<R, 3, SB, false>(u, psi, bb, acc); break;
+                    if (d < 6) {
+                        cx<R> psi[12];
+                        load_spinor_rsrc<S>(rin, a.in, g.Vh, r, nb[d], psi);
+                        switch (d) {
+                        case 0: hop_mul<R, 0, SF, true>(u, psi, acc); break;
+                        case 1: hop_mul<R, 0, SB, false>(u, psi, acc); break;
+                        case 2: hop_mul<R, 1, SF, true>(u, psi, acc); break;
+                        case 3: hop_mul<R, 1, SB, false>(u, psi, acc); break;
+                        case 4: hop_mul<R, 2, SF, true>(u, psi, acc); break;
+                        default: hop_mul<R, 2, SB, false>(u, psi, acc); break;
+                        }
+                    } else if (d == 6) {
+                        cx<R> half[6];
+                        load_half_rsrc<S, t_half<SF>()>(rin, a.in, g.Vh, r, nb[d], half);
+                        hop_mul_t<R, SF, true>(u, half, R(2) * bf, acc);
+                    } else {
+                        cx<R> half[6];
+                        load_half_rsrc<S, t_half<SB>()>(rin, a.in, g.Vh, r, nb[d], half);
+                        hop_mul_t<R, SB, false>(u, half, R(2) * bb, acc);
                     }
                     pin_acc<R>(acc);
                 }

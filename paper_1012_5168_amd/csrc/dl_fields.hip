@@ -1,6 +1,7 @@
-// dl_fields.hip -- layout conversion (canonical <-> even-odd SoA), noise and
-// point sources with dilution masks, the timeslice trace reduction and the
-// gamma contraction of the loops, and link-format conversion.
+// dl_fields.hip -- layout conversion (canonical <-> even-odd SoA, and the
+// chiral spin basis <-> the stored basis of dl_common.hpp), noise and point
+// sources with dilution masks, the timeslice trace reduction and the gamma
+// contraction of the loops, and link-format conversion.
 #include "dl_dslash.hpp"
 
 namespace dl {
@@ -85,12 +86,13 @@ __global__ __launch_bounds__(BS) void pack_kernel(Field dst, int parity, const d
     const Site s = decode(g, cb, parity);
     const int64_t V = 2 * (int64_t)g.Vh;
     const double2 *src = reinterpret_cast<const double2 *>(canon) + ((int64_t)rhs * V + lex_index(g, s)) * 12;
+    cx<double> z[12];
+#pragma unroll
+    for (int e = 0; e < 12; ++e) z[e] = {src[e].x, src[e].y};
+    to_internal(z);
     cx<R> v[12];
 #pragma unroll
-    for (int e = 0; e < 12; ++e) {
-        double2 z = src[e];
-        v[e] = {R(z.x), R(z.y)};
-    }
+    for (int e = 0; e < 12; ++e) v[e] = {R(z[e].re), R(z[e].im)};
     store_spinor<S>(dst, g.Vh, rhs, cb, v);
 }
 
@@ -106,8 +108,12 @@ __global__ __launch_bounds__(BS) void unpack_kernel(Field src, int parity, doubl
     double2 *dst = reinterpret_cast<double2 *>(canon) + ((int64_t)rhs * V + lex_index(g, s)) * 12;
     cx<R> v[12];
     load_spinor<S>(src, g.Vh, rhs, cb, v);
+    cx<double> z[12];
 #pragma unroll
-    for (int e = 0; e < 12; ++e) dst[e] = make_double2((double)v[e].re, (double)v[e].im);
+    for (int e = 0; e < 12; ++e) z[e] = {(double)v[e].re, (double)v[e].im};
+    to_canonical(z);
+#pragma unroll
+    for (int e = 0; e < 12; ++e) dst[e] = make_double2(z[e].re, z[e].im);
 }
 
 template <typename S>
@@ -120,6 +126,7 @@ __global__ __launch_bounds__(BS) void source_kernel(Field dst, int parity, Sourc
     const Site s = decode(g, cb, parity);
     cx<double> eta[12];
     source_site(src, rhs, s, lex_index(g, s), eta);
+    to_internal(eta);
     cx<R> v[12];
 #pragma unroll
     for (int e = 0; e < 12; ++e) v[e] = {R(eta[e].re), R(eta[e].im)};
@@ -144,12 +151,18 @@ __global__ __launch_bounds__(BS) void trace_kernel(Field se, Field so, SourceSpe
         const int cb = t * per + (j - par * per);
         const Site s = decode(g, cb, par);
         cx<double> eta[12];
-        if (src.kind == SRC_STORED)
+        if (src.kind == SRC_STORED) {
             load_spinor<double>(par ? src.xo : src.xe, g.Vh, rhs, cb, eta);
-        else
+            to_canonical(eta);
+        } else {
             source_site(src, rhs, s, lex_index(g, s), eta);
-        cx<R> sv[12];
-        load_spinor<S>(par ? so : se, g.Vh, rhs, cb, sv);
+        }
+        cx<R> sl[12];
+        load_spinor<S>(par ? so : se, g.Vh, rhs, cb, sl);
+        cx<double> sv[12];
+#pragma unroll
+        for (int e = 0; e < 12; ++e) sv[e] = {(double)sl[e].re, (double)sl[e].im};
+        to_canonical(sv);
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -158,7 +171,7 @@ __global__ __launch_bounds__(BS) void trace_kernel(Field se, Field so, SourceSpe
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const cx<double> e = eta[3 * a + c];
-                    const double vr = (double)sv[3 * b + c].re, vi = (double)sv[3 * b + c].im;
+                    const double vr = sv[3 * b + c].re, vi = sv[3 * b + c].im;
                     re += e.re * vr + e.im * vi;
                     im += e.re * vi - e.im * vr;
                 }
@@ -321,13 +334,21 @@ __global__ __launch_bounds__(BS) void adjoint_source_kernel(Field dst, int parit
             for (int b = 0; b < 4; ++b) cmac(acc, cx<double>{At[2 * (4 * a + b)], At[2 * (4 * a + b) + 1]}, eta[3 * b + c]);
             v[3 * a + c] = acc;
         }
+    to_internal(v);
     store_spinor<double>(dst, g.Vh, rhs, cb, v);
 }
 
-// load a full spinor and apply gamma5 = diag(1, 1, -1, -1) when g5 is set
-__device__ __forceinline__ void load_g5(const Field &f, int64_t Vh, int rhs, int64_t cb, bool g5, cx<double> v[12])
+// a stored FP64 spinor in the chiral basis
+__device__ __forceinline__ void load_chiral(const Field &f, int64_t Vh, int rhs, int64_t cb, cx<double> v[12])
 {
     load_spinor<double>(f, Vh, rhs, cb, v);
+    to_canonical(v);
+}
+
+// load a full spinor (chiral basis) and apply gamma5 = diag(1, 1, -1, -1) when g5 is set
+__device__ __forceinline__ void load_g5(const Field &f, int64_t Vh, int rhs, int64_t cb, bool g5, cx<double> v[12])
+{
+    load_chiral(f, Vh, rhs, cb, v);
     if (g5)
 #pragma unroll
         for (int e = 6; e < 12; ++e) v[e] = -v[e];
@@ -348,7 +369,7 @@ __device__ __forceinline__ void grad_dir(const Field &se, const Field &so, const
     const Field &sy = par ? se : so, &ay = par ? ae : ao;
     for (int r = 0; r < nrhs; ++r) {
         cx<double> v[12], h[6], ah[6];
-        load_spinor<double>(sy, g.Vh, r, cby, v);
+        load_chiral(sy, g.Vh, r, cby, v);
         project<double, MU, -1>(v, h);
         load_g5(ax, g.Vh, r, cbx, true, v);
         project<double, MU, -1>(v, ah);
@@ -362,7 +383,7 @@ __device__ __forceinline__ void grad_dir(const Field &se, const Field &so, const
                 cmac_conj(t, ah[3 + a], h[3 + c]);
                 X[3 * a + c] = t;
             }
-        load_spinor<double>(sx, g.Vh, r, cbx, v);
+        load_chiral(sx, g.Vh, r, cbx, v);
         project<double, MU, +1>(v, h);
         load_g5(ay, g.Vh, r, cby, true, v);
         project<double, MU, +1>(v, ah);
