@@ -150,6 +150,13 @@ def load(path: str | None = None):
     path = path or LIBRARY_PATH
     if not os.path.exists(path):
         raise RuntimeError("libdloops.so is not built (%s); run paper_1012_5168_amd._build.build()" % path)
+    # torch ships its own HIP runtime under the same soname as the system's: loaded first, it is the one
+    # the library binds to, so the process holds a single runtime (with the library loaded first, torch
+    # would load a second one and the first would find no device)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     for name, (res, args) in _SIGNATURES.items():
         f = getattr(lib, name)

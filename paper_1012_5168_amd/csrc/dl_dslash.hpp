@@ -15,6 +15,8 @@
 // its neighbour, half the bytes of a spatial one.
 #pragma once
 
+#include <type_traits>
+
 #include "dl_internal.hpp"
 
 namespace dl {
@@ -388,6 +390,33 @@ __device__ __forceinline__ void reserve_waves()
         asm volatile("" ::: "v191");
 }
 
+// Whether the LDS-link kernel double-buffers its neighbour loads.  Measured on
+// 288 right-hand sides at 16^3 x 32: FP64 (one wavefront per SIMD, registers
+// to spare) and BF16 gain 4-8%; FP32 runs at the occupancy it compiles to and
+// the second buffer costs it wavefronts (5% slower), so it walks one hop at a
+// time.
+template <typename S>
+constexpr bool lds_pipelined()
+{
+    return !std::is_same<S, float>::value;
+}
+
+// the per-(right-hand side, site block) partial sums of a reducing epilogue,
+// summed over the wavefront and written by its first lane
+template <int NP>
+__device__ __forceinline__ void write_block_partials(const DKArgs &a, int r, int sb, int sl, double part[])
+{
+    if constexpr (NP > 0) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) part[k] = wave_sum(part[k]);
+        if (sl == 0) {
+            double *dst = a.partials + ((int64_t)r * a.nblk + sb) * NP;
+#pragma unroll
+            for (int k = 0; k < NP; ++k) dst[k] = part[k];
+        }
+    }
+}
+
 template <typename S, int NE, bool DAG, int EPI, int LANES, int OCC>
 __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArgs> B, int rb)
 {
@@ -448,57 +477,122 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
             const bool on = rl < a.nrhs && (a.active == nullptr || a.active[rl] != 0);
             uint64_t m = __ballot(on);
             nlive += (unsigned)__popcll(m);
-            while (m != 0) {
-                const int r = r0 + __builtin_ctzll(m) * LANES;
+            if constexpr (lds_pipelined<S>()) {
+                // Neighbour spinors double-buffered: hop d + 1's loads are in
+                // flight while hop d computes, and the next right-hand side's
+                // first hop while the last hop and the epilogue of this one
+                // run.  The empty asm statements fence memory operations: the
+                // one after a hop's loads keeps them ahead of the previous
+                // hop's arithmetic, the accumulator pin after that arithmetic
+                // keeps the following loads behind it (without the fences the
+                // compiler issues all eight hops' loads at once and spills).
+                if (m == 0) continue;
+                int r = r0 + __builtin_ctzll(m) * LANES;
                 m &= m - 1;
-                const __amdgpu_buffer_rsrc_t rin = spinor_rsrc<S>(a.in, g.Vh, r);
-                double part[NP > 0 ? NP : 1];
+                __amdgpu_buffer_rsrc_t rin = spinor_rsrc<S>(a.in, g.Vh, r);
+                cx<R> pa[12], pb[12];
+                auto load_hop = [&](__amdgpu_buffer_rsrc_t rs, int rr, int d, cx<R> *dst) {
+                    if (d < 6)
+                        load_spinor_rsrc<S>(rs, a.in, g.Vh, rr, nb[d], dst);
+                    else if (d == 6)
+                        load_half_rsrc<S, t_half<SF>()>(rs, a.in, g.Vh, rr, nb[6], dst);
+                    else
+                        load_half_rsrc<S, t_half<SB>()>(rs, a.in, g.Vh, rr, nb[7], dst);
+                };
+                load_hop(rin, r, 0, pa);
+                while (true) {
+                    const bool more = m != 0;
+                    const int rn = more ? r0 + __builtin_ctzll(m) * LANES : r;
+                    m &= m - 1;
+                    const __amdgpu_buffer_rsrc_t rin_n = spinor_rsrc<S>(a.in, g.Vh, rn);
+                    double part[NP > 0 ? NP : 1];
 #pragma unroll
-                for (int k = 0; k < (NP > 0 ? NP : 1); ++k) part[k] = 0.0;
-                cx<R> acc[12];
+                    for (int k = 0; k < (NP > 0 ? NP : 1); ++k) part[k] = 0.0;
+                    cx<R> acc[12];
 #pragma unroll
-                for (int e = 0; e < 12; ++e) acc[e] = {R(0), R(0)};
+                    for (int e = 0; e < 12; ++e) acc[e] = {R(0), R(0)};
 #pragma unroll
-                for (int d = 0; d < 8; ++d) {
-                    cx<R> u[9];
+                    for (int d = 0; d < 8; ++d) {
+                        cx<R> *cur = (d & 1) ? pb : pa;
+                        // after the last right-hand side rn = r: the redundant
+                        // loads keep the issue unconditional, so the compiler
+                        // need not wait for them before this hop's arithmetic
+                        if (d + 1 < 8)
+                            load_hop(rin, r, d + 1, (d & 1) ? pa : pb);
+                        else
+                            load_hop(rin_n, rn, 0, pa);
+                        asm volatile("" ::: "memory");
+                        cx<R> u[9];
 #pragma unroll
-                    for (int e = 0; e < NE; ++e) u[e] = Fmt<S>::ld(lk, (d * NE + e) * LDS_SITES + sl);
-                    if constexpr (NE == 6) {
-                        u[6] = conj(u[1] * u[5] - u[2] * u[4]);
-                        u[7] = conj(u[2] * u[3] - u[0] * u[5]);
-                        u[8] = conj(u[0] * u[4] - u[1] * u[3]);
-                    }
-                    if (d < 6) {
-                        cx<R> psi[12];
-                        load_spinor_rsrc<S>(rin, a.in, g.Vh, r, nb[d], psi);
-                        switch (d) {
-                        case 0: hop_mul<R, 0, SF, true>(u, psi, acc); break;
-                        case 1: hop_mul<R, 0, SB, false>(u, psi, acc); break;
-                        case 2: hop_mul<R, 1, SF, true>(u, psi, acc); break;
-                        case 3: hop_mul<R, 1, SB, false>(u, psi, acc); break;
-                        case 4: hop_mul<R, 2, SF, true>(u, psi, acc); break;
-                        default: hop_mul<R, 2, SB, false>(u, psi, acc); break;
+                        for (int e = 0; e < NE; ++e) u[e] = Fmt<S>::ld(lk, (d * NE + e) * LDS_SITES + sl);
+                        if constexpr (NE == 6) {
+                            u[6] = conj(u[1] * u[5] - u[2] * u[4]);
+                            u[7] = conj(u[2] * u[3] - u[0] * u[5]);
+                            u[8] = conj(u[0] * u[4] - u[1] * u[3]);
                         }
-                    } else if (d == 6) {
-                        cx<R> half[6];
-                        load_half_rsrc<S, t_half<SF>()>(rin, a.in, g.Vh, r, nb[d], half);
-                        hop_mul_t<R, SF, true>(u, half, R(2) * bf, acc);
-                    } else {
-                        cx<R> half[6];
-                        load_half_rsrc<S, t_half<SB>()>(rin, a.in, g.Vh, r, nb[d], half);
-                        hop_mul_t<R, SB, false>(u, half, R(2) * bb, acc);
+                        switch (d) {
+                        case 0: hop_mul<R, 0, SF, true>(u, cur, acc); break;
+                        case 1: hop_mul<R, 0, SB, false>(u, cur, acc); break;
+                        case 2: hop_mul<R, 1, SF, true>(u, cur, acc); break;
+                        case 3: hop_mul<R, 1, SB, false>(u, cur, acc); break;
+                        case 4: hop_mul<R, 2, SF, true>(u, cur, acc); break;
+                        case 5: hop_mul<R, 2, SB, false>(u, cur, acc); break;
+                        case 6: hop_mul_t<R, SF, true>(u, cur, R(2) * bf, acc); break;
+                        default: hop_mul_t<R, SB, false>(u, cur, R(2) * bb, acc); break;
+                        }
+                        pin_acc<R>(acc);
                     }
-                    pin_acc<R>(acc);
+                    epilogue<S, EPI, true, true>(a, r, cb, acc, part, valid);
+                    write_block_partials<NP>(a, r, sb, sl, part);
+                    if (!more) break;
+                    r = rn;
+                    rin = rin_n;
                 }
-                epilogue<S, EPI, true, true>(a, r, cb, acc, part, valid);
-                if constexpr (NP > 0) {
+            } else {
+                while (m != 0) {
+                    const int r = r0 + __builtin_ctzll(m) * LANES;
+                    m &= m - 1;
+                    const __amdgpu_buffer_rsrc_t rin = spinor_rsrc<S>(a.in, g.Vh, r);
+                    double part[NP > 0 ? NP : 1];
 #pragma unroll
-                    for (int k = 0; k < NP; ++k) part[k] = wave_sum(part[k]);
-                    if (sl == 0) {
-                        double *dst = a.partials + ((int64_t)r * a.nblk + sb) * NP;
+                    for (int k = 0; k < (NP > 0 ? NP : 1); ++k) part[k] = 0.0;
+                    cx<R> acc[12];
 #pragma unroll
-                        for (int k = 0; k < NP; ++k) dst[k] = part[k];
+                    for (int e = 0; e < 12; ++e) acc[e] = {R(0), R(0)};
+#pragma unroll
+                    for (int d = 0; d < 8; ++d) {
+                        cx<R> u[9];
+#pragma unroll
+                        for (int e = 0; e < NE; ++e) u[e] = Fmt<S>::ld(lk, (d * NE + e) * LDS_SITES + sl);
+                        if constexpr (NE == 6) {
+                            u[6] = conj(u[1] * u[5] - u[2] * u[4]);
+                            u[7] = conj(u[2] * u[3] - u[0] * u[5]);
+                            u[8] = conj(u[0] * u[4] - u[1] * u[3]);
+                        }
+                        if (d < 6) {
+                            cx<R> psi[12];
+                            load_spinor_rsrc<S>(rin, a.in, g.Vh, r, nb[d], psi);
+                            switch (d) {
+                            case 0: hop_mul<R, 0, SF, true>(u, psi, acc); break;
+                            case 1: hop_mul<R, 0, SB, false>(u, psi, acc); break;
+                            case 2: hop_mul<R, 1, SF, true>(u, psi, acc); break;
+                            case 3: hop_mul<R, 1, SB, false>(u, psi, acc); break;
+                            case 4: hop_mul<R, 2, SF, true>(u, psi, acc); break;
+                            default: hop_mul<R, 2, SB, false>(u, psi, acc); break;
+                            }
+                        } else if (d == 6) {
+                            cx<R> half[6];
+                            load_half_rsrc<S, t_half<SF>()>(rin, a.in, g.Vh, r, nb[d], half);
+                            hop_mul_t<R, SF, true>(u, half, R(2) * bf, acc);
+                        } else {
+                            cx<R> half[6];
+                            load_half_rsrc<S, t_half<SB>()>(rin, a.in, g.Vh, r, nb[d], half);
+                            hop_mul_t<R, SB, false>(u, half, R(2) * bb, acc);
+                        }
+                        pin_acc<R>(acc);
                     }
+                    epilogue<S, EPI, true, true>(a, r, cb, acc, part, valid);
+                    write_block_partials<NP>(a, r, sb, sl, part);
                 }
             }
         }
