@@ -386,10 +386,7 @@ static void dslash_bytes(const DslashCall &c, double &per_rhs, double &links)
     per_rhs = nfield * field;
 }
 
-bool dslash_lds_ok(int prec, int recon)
-{
-    return 8.0 * (recon == 12 ? 6 : 9) * 64 * (double)elem_bytes(prec) <= 65536.0;
-}
+bool dslash_lds_ok(int prec, int recon) { return lds_link_block_bytes(prec, recon) <= LDS_WORKGROUP_BYTES; }
 
 int dslash_block_sites(const DslashCall &c, const TuneChoice &t)
 {

@@ -357,7 +357,9 @@ __global__ __launch_bounds__(256) void dslash_kernel(Segs<DKArgs> B)
 // ---------------------------------------------------------------- LDS-link kernel
 //
 // A workgroup owns 64 consecutive checkerboard sites (one wavefront wide) and
-// keeps their 8 x NE link matrices in LDS; its LANES wavefronts then walk the
+// keeps their 8 link matrices in LDS, expanded to all three rows in the
+// arithmetic precision (converted and rebuilt once per block, not once per
+// right-hand side and hop); its LANES wavefronts then walk the
 // right-hand sides (wavefront w takes w, w + LANES, ...), so every link is
 // read from memory once per launch instead of once per right-hand side.
 // Site blocks are grouped into regions of rb consecutive blocks; region i
@@ -368,10 +370,20 @@ __global__ __launch_bounds__(256) void dslash_kernel(Segs<DKArgs> B)
 // (right-hand side, 64-site block).
 constexpr int LDS_SITES = 64;
 
+// Whether the LDS holds the links expanded (9 complex numbers per link in the
+// arithmetic precision) or as stored (NE entries in the storage format,
+// converted and completed per use).
+template <typename S, int NE>
+constexpr bool lds_expanded()
+{
+    return !LDS_COMPACT_LINKS;
+}
+
 template <typename S, int NE>
 constexpr int lds_link_bytes()
 {
-    return 8 * NE * LDS_SITES * (int)sizeof(typename Fmt<S>::E);
+    return lds_expanded<S, NE>() ? 8 * 9 * LDS_SITES * (int)sizeof(cx<typename Fmt<S>::R>)
+                                 : 8 * NE * LDS_SITES * (int)sizeof(typename Fmt<S>::E);
 }
 
 // Reserve registers so that at most OCC wavefronts share a SIMD (0: the
@@ -425,8 +437,25 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
     constexpr int NP = nparts_c<EPI>();
     constexpr int SF = DAG ? +1 : -1;
     constexpr int SB = -SF;
-    __shared__ E lk[8 * NE * LDS_SITES];
+    __shared__ __align__(16) unsigned char lds[lds_link_bytes<S, NE>()];
+    E *const lk = reinterpret_cast<E *>(lds);           // links as stored
+    cx<R> *const lx = reinterpret_cast<cx<R> *>(lds);   // links expanded
     reserve_waves<OCC>();
+    // the link of hop d at this lane's site, all three rows
+    auto load_u = [&](int d, int sl_, cx<R> u[9]) {
+        if constexpr (lds_expanded<S, NE>()) {
+#pragma unroll
+            for (int e = 0; e < 9; ++e) u[e] = lx[(d * 9 + e) * LDS_SITES + sl_];
+        } else {
+#pragma unroll
+            for (int e = 0; e < NE; ++e) u[e] = Fmt<S>::ld(lk, (d * NE + e) * LDS_SITES + sl_);
+            if constexpr (NE == 6) {
+                u[6] = conj(u[1] * u[5] - u[2] * u[4]);
+                u[7] = conj(u[2] * u[3] - u[0] * u[5]);
+                u[8] = conj(u[0] * u[4] - u[1] * u[3]);
+            }
+        }
+    };
 
     // w is the wavefront's index, uniform across it: said so explicitly, the
     // per-right-hand-side buffer resources below stay in scalar registers
@@ -460,8 +489,15 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
             const int mu = d >> 1, bwd = d & 1;
             const int lcb = bwd ? nb[d] : cb;
             const E *src = static_cast<const E *>(a.links) + ((int64_t)(mu * 2 + (bwd ? q : p)) * NE) * g.Vh + lcb;
+            if constexpr (lds_expanded<S, NE>()) {
+                cx<R> u[9];
+                load_link<S, NE>(a.links, g.Vh, mu, bwd ? q : p, lcb, u);
 #pragma unroll
-            for (int e = 0; e < NE; ++e) lk[(d * NE + e) * LDS_SITES + sl] = src[(int64_t)e * g.Vh];
+                for (int e = 0; e < 9; ++e) lx[(d * 9 + e) * LDS_SITES + sl] = u[e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < NE; ++e) lk[(d * NE + e) * LDS_SITES + sl] = src[(int64_t)e * g.Vh];
+            }
         }
         __syncthreads();
 
@@ -523,13 +559,7 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
                             load_hop(rin_n, rn, 0, pa);
                         asm volatile("" ::: "memory");
                         cx<R> u[9];
-#pragma unroll
-                        for (int e = 0; e < NE; ++e) u[e] = Fmt<S>::ld(lk, (d * NE + e) * LDS_SITES + sl);
-                        if constexpr (NE == 6) {
-                            u[6] = conj(u[1] * u[5] - u[2] * u[4]);
-                            u[7] = conj(u[2] * u[3] - u[0] * u[5]);
-                            u[8] = conj(u[0] * u[4] - u[1] * u[3]);
-                        }
+                        load_u(d, sl, u);
                         switch (d) {
                         case 0: hop_mul<R, 0, SF, true>(u, cur, acc); break;
                         case 1: hop_mul<R, 0, SB, false>(u, cur, acc); break;
@@ -562,13 +592,7 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
 #pragma unroll
                     for (int d = 0; d < 8; ++d) {
                         cx<R> u[9];
-#pragma unroll
-                        for (int e = 0; e < NE; ++e) u[e] = Fmt<S>::ld(lk, (d * NE + e) * LDS_SITES + sl);
-                        if constexpr (NE == 6) {
-                            u[6] = conj(u[1] * u[5] - u[2] * u[4]);
-                            u[7] = conj(u[2] * u[3] - u[0] * u[5]);
-                            u[8] = conj(u[0] * u[4] - u[1] * u[3]);
-                        }
+                        load_u(d, sl, u);
                         if (d < 6) {
                             cx<R> psi[12];
                             load_spinor_rsrc<S>(rin, a.in, g.Vh, r, nb[d], psi);

@@ -23,7 +23,7 @@ static void dslash_go_lds(const Segs<DKArgs> &B, int occ, int grid, int rb, hipS
 template <typename S, int NE, bool DAG, int EPI>
 static void dslash_go_nr(const Segs<DKArgs> &B, int kind, int nr, int grid, int bs, int rb, hipStream_t s)
 {
-    if constexpr (lds_link_bytes<S, NE>() <= 65536) {
+    if constexpr (lds_link_bytes<S, NE>() <= LDS_WORKGROUP_BYTES) {
         if (kind == 1) {
             if (nr == 4)
                 dslash_go_lds<S, NE, DAG, EPI, 4>(B, bs, grid, rb, s);
@@ -58,7 +58,7 @@ static void dslash_go_epi(const Segs<DKArgs> &B, int epi, int kind, int nr, int 
 template <typename S>
 bool dslash_lds_ok_t(int recon)
 {
-    return recon == 12 ? lds_link_bytes<S, 6>() <= 65536 : lds_link_bytes<S, 9>() <= 65536;
+    return recon == 12 ? lds_link_bytes<S, 6>() <= LDS_WORKGROUP_BYTES : lds_link_bytes<S, 9>() <= LDS_WORKGROUP_BYTES;
 }
 
 // c[0..nseg): calls with the same precision, link format, adjoint flag and

@@ -205,8 +205,21 @@ struct TuneChoice {
 TuneChoice tune_lookup(const std::vector<DslashCall> &c, hipStream_t s);
 void launch_dslash_any(const std::vector<DslashCall> &c, const TuneChoice &t, hipStream_t s);
 // whether the LDS-link kernel serves this precision and link format (its
-// links must fit 64 KiB of LDS), and the sites per block a choice gives
+// links must fit the LDS a workgroup may hold), and the sites per block a choice gives
 bool dslash_lds_ok(int prec, int recon);
+// LDS a workgroup may hold on gfx950
+constexpr int LDS_WORKGROUP_BYTES = 163840;
+// links in the LDS-link kernel's LDS: expanded to three rows in the arithmetic
+// precision (0), or as stored (1: the variant that rebuilds them per use)
+#ifndef LDS_COMPACT_LINKS
+#define LDS_COMPACT_LINKS 0
+#endif
+// bytes of links one 64-site block of the LDS-link kernel keeps in LDS
+inline int lds_link_block_bytes(int prec, int recon)
+{
+    return LDS_COMPACT_LINKS ? 8 * (recon == 12 ? 6 : 9) * 64 * (int)elem_bytes(prec)
+                             : 8 * 9 * 64 * (prec == P64 ? 16 : 8);
+}
 int dslash_block_sites(const DslashCall &c, const TuneChoice &t);
 
 // ---------------------------------------------------------------- Krylov vector kernels
