@@ -382,7 +382,7 @@ static void dslash_bytes(const DslashCall &c, double &per_rhs, double &links)
     links = vh * 8.0 * (c.recon == 12 ? 6 : 9) * e;
     int nfield = 2;  // in, out
     if (c.epi != EPI_PLAIN) nfield += 1;                             // x
-    if (c.epi == EPI_XPAY_DOT || c.epi == EPI_XMY_NRM) nfield += 1;  // y
+    if (c.epi == EPI_XPAY_DOT || c.epi == EPI_XMY_NRM || c.epi == EPI_XPAY_TS) nfield += 1;  // y
     per_rhs = nfield * field;
 }
 
@@ -860,18 +860,21 @@ struct SolveWork {
         act.alloc(sizeof(int) * n);
         upd.alloc(sizeof(int) * n);
         restart.alloc(sizeof(int) * n);
-        parts.alloc(sizeof(double) * 3 * (size_t)n * nblk_max);
+        // partial sums per (right-hand side, site block): up to five per block
+        // (the hop that makes t), and a second set that lives across a kernel
+        // in between ((rhat, s) of the s update, FP64 residual norms)
+        parts.alloc(sizeof(double) * 5 * (size_t)n * nblk_max);
         parts2.alloc(sizeof(double) * 3 * (size_t)n * nblk_max);
     }
     static size_t bytes_bicg(int prec, int64_t Vh)
     {
         size_t f64 = 12 * 16 * Vh, fl = 12 * elem_bytes(prec) * Vh + (prec == P16 ? 4 * Vh : 0);
-        return 7 * f64 + (prec == P64 ? 6 : 7) * fl + 6 * 8 * ((Vh + 63) / 64) + 256;
+        return 7 * f64 + (prec == P64 ? 6 : 7) * fl + 8 * 8 * ((Vh + 63) / 64) + 256;
     }
     static size_t bytes_cgnr(int prec, int64_t Vh)
     {
         size_t fl = 12 * elem_bytes(prec) * Vh + (prec == P16 ? 4 * Vh : 0);
-        return 10 * fl + 6 * 8 * ((Vh + 63) / 64) + 256;
+        return 10 * fl + 8 * 8 * ((Vh + 63) / 64) + 256;
     }
 };
 
@@ -957,15 +960,21 @@ std::vector<int> blas_nb(const std::vector<Prob> &P)
 }
 const int *mask_restart(const Prob &p) { return p.w->restart.as<int>(); }
 
-// the launches of one BiCGStab iteration over all problems
+// The launches of one BiCGStab iteration over all problems.  The search
+// direction p of this iteration is in place (from the previous iteration's
+// fused update, or p = r after a (re)start):
+//   v = Mhat p, alpha = rho / (rhat, v);  s = r - alpha v with (rhat, s);
+//   t = Mhat s, omega = (t, s) / |t|^2, rho' = (rhat, s) - omega (rhat, t),
+//   beta = (rho' / rho)(alpha / omega);
+//   x += alpha p + omega s, r = s - omega t, p = r + beta (p - omega v) in one
+//   pass with |r|^2; then the iteration count, convergence and reliable-update
+//   flags.  rho' follows from the linearity of (rhat, .) in r = s - omega t,
+//   which lets the p update join the x / r update (twelve field passes of
+//   vector kernels per iteration instead of fourteen, for one more read of
+//   rhat in the epilogue of the hop that makes t).
 void bicg_iteration(const std::vector<Prob> &P, int prec, bool mixed, hipStream_t s)
 {
     auto act = [](const Prob &p) { return p.w->act.as<int>(); };
-    vec_launch(V_BICG_P, prec, VS(P, [&](const Prob &p) {
-                   return vs({p.w->p.view(), p.w->r.view(), p.w->v.view()}, p.Vh(), p.w->n, act(p), nullptr,
-                             p.w->st.as<KState>());
-               }),
-               s);
     launch_dslash_batch(DS(P, [&](const Prob &p) {
                             return dcall(p.c, prec, 1, false, EPI_PLAIN, p.w->p.view(), p.w->tmpo.view(), NOF, NOF,
                                          1.0, p.w->n, nullptr, act(p));
@@ -980,7 +989,8 @@ void bicg_iteration(const std::vector<Prob> &P, int prec, bool mixed, hipStream_
                                                s);
     scalar_launch(S_BICG_ALPHA, SS(P, nbd, false, nullptr), SParams{}, s);
     vec_launch(V_BICG_S, prec, VS(P, [&](const Prob &p) {
-                   return vs({p.w->r.view(), p.w->v.view()}, p.Vh(), p.w->n, act(p), nullptr, p.w->st.as<KState>());
+                   return vs({p.w->r.view(), p.w->v.view(), p.w->rh.view()}, p.Vh(), p.w->n, act(p),
+                             p.w->parts2.as<double>(), p.w->st.as<KState>());
                }),
                s);
     launch_dslash_batch(DS(P, [&](const Prob &p) {
@@ -990,22 +1000,22 @@ void bicg_iteration(const std::vector<Prob> &P, int prec, bool mixed, hipStream_
                         s);
     nbd = launch_dslash_batch(DS(P, [&](const Prob &p) {
                                   return dcall(p.c, prec, 0, false, EPI_XPAY_TS, p.w->tmpo.view(), p.w->t.view(),
-                                               p.w->r.view(), NOF, -p.kappa * p.kappa, p.w->n, p.w->parts.as<double>(),
-                                               act(p));
+                                               p.w->r.view(), p.w->rh.view(), -p.kappa * p.kappa, p.w->n,
+                                               p.w->parts.as<double>(), act(p));
                               }),
                               s);
-    scalar_launch(S_BICG_OMEGA, SS(P, nbd, false, nullptr), SParams{}, s);
-    vec_launch(V_BICG_XR, prec, VS(P, [&](const Prob &p) {
+    std::vector<SSeg> om = SS(P, nbd, true, nullptr);
+    for (size_t k = 0; k < P.size(); ++k) om[k].nblk2 = P[k].nb();
+    scalar_launch(S_BICG_OMEGA, om, SParams{}, s);
+    vec_launch(V_BICG_XRP, prec, VS(P, [&](const Prob &p) {
                    Field xit = mixed ? p.w->xlo.view() : p.w->x64.view();
-                   return vs({xit, p.w->r.view(), p.w->p.view(), p.w->t.view(), p.w->rh.view()}, p.Vh(), p.w->n,
+                   return vs({xit, p.w->r.view(), p.w->p.view(), p.w->t.view(), p.w->v.view()}, p.Vh(), p.w->n,
                              act(p), p.w->parts.as<double>(), p.w->st.as<KState>());
                }),
                s);
     SParams sp;
-    sp.np = 3;
-    sp.first = 0;
     sp.mixed = mixed ? 1 : 0;
-    scalar_launch(S_BICG_RHO, SS(P, blas_nb(P), false, nullptr), sp, s);
+    scalar_launch(S_BICG_CHECK, SS(P, blas_nb(P), false, nullptr), sp, s);
 }
 
 int count_host(const DevBuf &flags, int n, hipStream_t s, std::vector<int> &h)
@@ -1153,16 +1163,13 @@ void bicgstab_multi(const std::vector<Prob> &P0, const dl_solve_params &prm, hip
                 s);
     copy_launch(prec, prec, VS(P, [&](const Prob &p) { return vs({p.w->rh.view(), p.w->r.view()}, p.Vh(), p.w->n); }),
                 s);
-    vec_launch(V_ZERO, prec, VS(P, [&](const Prob &p) { return vs({p.w->p.view()}, p.Vh(), p.w->n); }), s);
-    vec_launch(V_ZERO, prec, VS(P, [&](const Prob &p) { return vs({p.w->v.view()}, p.Vh(), p.w->n); }), s);
+    copy_launch(prec, prec, VS(P, [&](const Prob &p) { return vs({p.w->p.view(), p.w->r.view()}, p.Vh(), p.w->n); }),
+                s);
     vec_launch(V_DOT, prec, VS(P, [&](const Prob &p) {
                    return vs({p.w->rh.view(), p.w->r.view()}, p.Vh(), p.w->n, nullptr, p.w->parts.as<double>());
                }),
                s);
     SParams sr;
-    sr.np = 2;
-    sr.first = 1;
-    sr.mixed = mixed;
     scalar_launch(S_BICG_RHO, SS(P, blas_nb(P), false, nullptr), sr, s);
 
     const int poll = parse_poll(prm);
@@ -1210,22 +1217,27 @@ void bicgstab_multi(const std::vector<Prob> &P0, const dl_solve_params &prm, hip
                                                                          p.w->parts2.as<double>(), upd(p));
                                                         }),
                                                         s);
-            copy_launch(prec, P64, VS(P, [&](const Prob &p) {
-                            return vs({p.w->r.view(), p.w->r64.view()}, p.Vh(), p.w->n, upd(p));
-                        }),
-                        s);
+            // r <- the FP64 residual, p moved by the same difference (p holds
+            // r + beta (p - omega v) already) and rho <- (rhat, r) of the new r
+            replace_launch(prec, VS(P, [&](const Prob &p) {
+                               return vs({p.w->r.view(), p.w->r64.view(), p.w->p.view(), p.w->rh.view()}, p.Vh(),
+                                         p.w->n, upd(p), p.w->parts.as<double>());
+                           }),
+                           s);
+            scalar_launch(S_BICG_RESYNC, SS(P, blas_nb(P), false, upd), SParams{}, s);
             // residual norms are in parts2 for this check
             std::vector<SSeg> tr = SS(P, nb64, false, nullptr);
             for (size_t k = 0; k < P.size(); ++k) tr[k].parts = P[k].w->parts2.as<double>();
             scalar_launch(S_TRUE_RES, tr, SParams{}, s);
+            // restart from the true residual: rhat = r, p = r
             copy_launch(prec, prec, VS(P, [&](const Prob &p) {
                             return vs({p.w->rh.view(), p.w->r.view()}, p.Vh(), p.w->n, mask_restart(p));
                         }),
                         s);
-            vec_launch(V_ZERO, prec,
-                       VS(P, [&](const Prob &p) { return vs({p.w->p.view()}, p.Vh(), p.w->n, mask_restart(p)); }), s);
-            vec_launch(V_ZERO, prec,
-                       VS(P, [&](const Prob &p) { return vs({p.w->v.view()}, p.Vh(), p.w->n, mask_restart(p)); }), s);
+            copy_launch(prec, prec, VS(P, [&](const Prob &p) {
+                            return vs({p.w->p.view(), p.w->r.view()}, p.Vh(), p.w->n, mask_restart(p));
+                        }),
+                        s);
             vec_launch(V_DOT, prec, VS(P, [&](const Prob &p) {
                            return vs({p.w->rh.view(), p.w->r.view()}, p.Vh(), p.w->n, mask_restart(p),
                                      p.w->parts.as<double>());

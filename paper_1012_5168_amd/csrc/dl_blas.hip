@@ -69,36 +69,47 @@ __device__ void bicg_init(const SSeg &a, const SParams &p, int rhs)
     a.upd[rhs] = 0;
 }
 
-// rho_new = (rhat, r) from partials [.., 2 or 3] (|r|^2 third when np = 3)
+// (Re)start of the recursion: rho = (rhat, r) from partials [.., 2] (with
+// rhat = r, so |r|^2 is its real part), alpha = omega = 1.
 __device__ void bicg_rho(const SSeg &a, const SParams &p, int rhs)
 {
     if (masked_off(a.mask, rhs)) return;
-    if (!p.first && !a.act[rhs]) return;
-    double rn[2] = {sum_parts(a.parts, rhs, a.nblk, p.np, 0), sum_parts(a.parts, rhs, a.nblk, p.np, 1)};
-    double rr = p.np == 3 ? sum_parts(a.parts, rhs, a.nblk, p.np, 2) : rn[0];
+    double rn[2] = {sum_parts(a.parts, rhs, a.nblk, 2, 0), sum_parts(a.parts, rhs, a.nblk, 2, 1)};
     if (threadIdx.x != 0) return;
     KState s = a.st[rhs];
-    if (p.first) {
-        // (re)start: rho = alpha = omega = 1, p = v = 0, so beta = rho_new
-        s.rho[0] = s.alpha[0] = s.omega[0] = 1.0;
-        s.rho[1] = s.alpha[1] = s.omega[1] = 0.0;
-        s.maxrr = rr;
-    } else {
-        s.iters += 1;
-    }
-    double q[2], ao[2];
-    cdiv(rn, s.rho, q);
-    cdiv(s.alpha, s.omega, ao);
-    cmul(q, ao, s.beta);
     s.rho[0] = rn[0];
     s.rho[1] = rn[1];
+    s.alpha[0] = s.omega[0] = 1.0;
+    s.alpha[1] = s.omega[1] = 0.0;
+    s.beta[0] = s.beta[1] = 0.0;
+    s.rr = rn[0];
+    s.maxrr = rn[0];
+    if (!isfinite(rn[0]) || !isfinite(rn[1])) {
+        s.nonfinite = 1;
+        a.act[rhs] = 0;
+        a.upd[rhs] = 0;
+    }
+    a.st[rhs] = s;
+}
+
+// After the x / r / p update of an iteration: |r|^2 from partials [.., 1];
+// counts the iteration and flags convergence (or the iteration cap, or a
+// breakdown rho = 0) for the FP64 true-residual check, and a reliable update
+// when |r| fell by delta since the last one.
+__device__ void bicg_check(const SSeg &a, const SParams &p, int rhs)
+{
+    if (!a.act[rhs]) return;
+    const double rr = sum_parts(a.parts, rhs, a.nblk, 1, 0);
+    if (threadIdx.x != 0) return;
+    KState s = a.st[rhs];
+    s.iters += 1;
     s.rr = rr;
     if (!isfinite(rr) || !isfinite(s.beta[0]) || !isfinite(s.beta[1])) {
         s.nonfinite = 1;
         a.act[rhs] = 0;
         a.upd[rhs] = 0;
-    } else if (!p.first) {
-        if (rr <= s.stop2 || s.iters >= s.maxiter || (rn[0] == 0 && rn[1] == 0)) {
+    } else {
+        if (rr <= s.stop2 || s.iters >= s.maxiter || (s.rho[0] == 0 && s.rho[1] == 0)) {
             // converged (or out of iterations, or breakdown): check the FP64 true residual
             a.act[rhs] = 0;
             a.upd[rhs] = 1;
@@ -121,11 +132,19 @@ __device__ void bicg_alpha(const SSeg &a, int rhs)
     a.st[rhs] = s;
 }
 
+// omega = (t, s) / |t|^2 from the partials of the hop that made t ([.., 5]:
+// (t, s), |t|^2, (rhat, t)); the next rho by linearity of r = s - omega t,
+// rho' = (rhat, s) - omega (rhat, t), with (rhat, s) from parts2 [.., 2] (the
+// s update); beta = (rho' / rho) (alpha / omega).  Each dot is taken directly
+// from the vectors of this iteration: nothing accumulates across iterations.
 __device__ void bicg_omega(const SSeg &a, int rhs)
 {
     if (!a.act[rhs]) return;
-    double ts[2] = {sum_parts(a.parts, rhs, a.nblk, 3, 0), sum_parts(a.parts, rhs, a.nblk, 3, 1)};
-    double tt = sum_parts(a.parts, rhs, a.nblk, 3, 2);
+    const int nb2 = a.nblk2 > 0 ? a.nblk2 : a.nblk;
+    double ts[2] = {sum_parts(a.parts, rhs, a.nblk, 5, 0), sum_parts(a.parts, rhs, a.nblk, 5, 1)};
+    double tt = sum_parts(a.parts, rhs, a.nblk, 5, 2);
+    double rt[2] = {sum_parts(a.parts, rhs, a.nblk, 5, 3), sum_parts(a.parts, rhs, a.nblk, 5, 4)};
+    double rs[2] = {sum_parts(a.parts2, rhs, nb2, 2, 0), sum_parts(a.parts2, rhs, nb2, 2, 1)};
     if (threadIdx.x != 0) return;
     KState s = a.st[rhs];
     if (tt > 0) {
@@ -134,7 +153,28 @@ __device__ void bicg_omega(const SSeg &a, int rhs)
     } else {
         s.omega[0] = s.omega[1] = 0.0;
     }
+    double wrt[2], rn[2], q[2], ao[2];
+    cmul(s.omega, rt, wrt);
+    rn[0] = rs[0] - wrt[0];
+    rn[1] = rs[1] - wrt[1];
+    cdiv(rn, s.rho, q);
+    cdiv(s.alpha, s.omega, ao);
+    cmul(q, ao, s.beta);
+    s.rho[0] = rn[0];
+    s.rho[1] = rn[1];
     a.st[rhs] = s;
+}
+
+// After a reliable update replaced r by the FP64 residual (partials [.., 2]:
+// (rhat, r) of the replaced r): rho takes that value, so that the next alpha
+// matches the r it multiplies; alpha, omega and beta stay.
+__device__ void bicg_resync(const SSeg &a, int rhs)
+{
+    if (masked_off(a.mask, rhs)) return;
+    double rn[2] = {sum_parts(a.parts, rhs, a.nblk, 2, 0), sum_parts(a.parts, rhs, a.nblk, 2, 1)};
+    if (threadIdx.x != 0) return;
+    a.st[rhs].rho[0] = rn[0];
+    a.st[rhs].rho[1] = rn[1];
 }
 
 // after an FP64 residual recomputation (parts: |r_e|^2 [, parts2: |r_o|^2])
@@ -232,6 +272,8 @@ __global__ __launch_bounds__(64) void scalar_kernel(Segs<SSeg> B, SParams p)
         else if constexpr (OP == S_BICG_RHO) bicg_rho(a, p, rhs);
         else if constexpr (OP == S_BICG_ALPHA) bicg_alpha(a, rhs);
         else if constexpr (OP == S_BICG_OMEGA) bicg_omega(a, rhs);
+        else if constexpr (OP == S_BICG_CHECK) bicg_check(a, p, rhs);
+        else if constexpr (OP == S_BICG_RESYNC) bicg_resync(a, rhs);
         else if constexpr (OP == S_TRUE_RES) true_residual(a, p, rhs);
         else if constexpr (OP == S_CG_INIT) cg_init(a, p, rhs);
         else if constexpr (OP == S_CG_ALPHA) cg_alpha(a, rhs);
@@ -253,14 +295,14 @@ __device__ __forceinline__ void write_parts(double v[NP], double *red, double *p
 }
 
 // f[0..4] by operation:
-//   V_BICG_P  p = r + beta (p - omega v)                                        f: p, r, v
-//   V_BICG_S  r = r - alpha v                                                   f: r, v
-//   V_BICG_XR x += alpha p + omega s; r = s - omega t; parts (rhat, r), |r|^2   f: x, r(s), p, t, rhat
-//   V_CG_XR   r -= alpha q; parts |r|^2                                         f: r, q
-//   V_CG_P    x += alpha p; p = r + beta p                                      f: p, r, x
-//   V_ZERO    f0 = 0
-//   V_NORM2   parts |f0|^2
-//   V_DOT     parts (f0, f1)
+//   V_BICG_S   s = r - alpha v (in r's storage); parts (rhat, s)                   f: r, v, rhat
+//   V_BICG_XRP x += alpha p + omega s; r = s - omega t; p = r + beta (p - omega v);
+//              parts |r|^2                                                          f: x, r(s), p, t, v
+//   V_CG_XR    r -= alpha q; parts |r|^2                                            f: r, q
+//   V_CG_P     x += alpha p; p = r + beta p                                         f: p, r, x
+//   V_ZERO     f0 = 0
+//   V_NORM2    parts |f0|^2
+//   V_DOT      parts (f0, f1)
 template <typename S, int OP>
 __device__ __forceinline__ void vec_item(const VSeg &a, int item, double *red)
 {
@@ -272,47 +314,46 @@ __device__ __forceinline__ void vec_item(const VSeg &a, int item, double *red)
     const int64_t Vh = a.Vh;
     const int64_t cb = (int64_t)blk * BS + threadIdx.x;
     const bool valid = cb < Vh;
-    if constexpr (OP == V_BICG_P) {
-        if (!valid) return;
-        const cx<R> beta = ld_c<R>(a.st[rhs].beta), omega = ld_c<R>(a.st[rhs].omega);
-        cx<R> pv[12], rv[12], vv[12];
-        load_spinor<S, true>(a.f[0], Vh, rhs, cb, pv);
-        load_spinor<S, true>(a.f[1], Vh, rhs, cb, rv);
-        load_spinor<S, true>(a.f[2], Vh, rhs, cb, vv);
-#pragma unroll
-        for (int e = 0; e < 12; ++e) pv[e] = rv[e] + beta * (pv[e] - omega * vv[e]);
-        store_spinor<S, true>(a.f[0], Vh, rhs, cb, pv);
-    } else if constexpr (OP == V_BICG_S) {
-        if (!valid) return;
-        const cx<R> alpha = ld_c<R>(a.st[rhs].alpha);
-        cx<R> rv[12], vv[12];
-        load_spinor<S, true>(a.f[0], Vh, rhs, cb, rv);
-        load_spinor<S, true>(a.f[1], Vh, rhs, cb, vv);
-#pragma unroll
-        for (int e = 0; e < 12; ++e) rv[e] = rv[e] - alpha * vv[e];
-        store_spinor<S, true>(a.f[0], Vh, rhs, cb, rv);
-    } else if constexpr (OP == V_BICG_XR) {
-        double part[3] = {0, 0, 0};
+    if constexpr (OP == V_BICG_S) {
+        double part[2] = {0, 0};
         if (valid) {
-            const cx<R> alpha = ld_c<R>(a.st[rhs].alpha), omega = ld_c<R>(a.st[rhs].omega);
-            cx<R> xv[12], sv[12], pv[12], tv[12], hv[12];
+            const cx<R> alpha = ld_c<R>(a.st[rhs].alpha);
+            cx<R> rv[12], vv[12], hv[12];
+            load_spinor<S, true>(a.f[0], Vh, rhs, cb, rv);
+            load_spinor<S, true>(a.f[1], Vh, rhs, cb, vv);
+            load_spinor<S, true>(a.f[2], Vh, rhs, cb, hv);
+#pragma unroll
+            for (int e = 0; e < 12; ++e) {
+                rv[e] = rv[e] - alpha * vv[e];
+                part[0] += (double)hv[e].re * rv[e].re + (double)hv[e].im * rv[e].im;
+                part[1] += (double)hv[e].re * rv[e].im - (double)hv[e].im * rv[e].re;
+            }
+            store_spinor<S, true>(a.f[0], Vh, rhs, cb, rv);
+        }
+        write_parts<2>(part, red, a.parts, rhs, nb, blk);
+    } else if constexpr (OP == V_BICG_XRP) {
+        double part[1] = {0};
+        if (valid) {
+            const KState &k = a.st[rhs];
+            const cx<R> alpha = ld_c<R>(k.alpha), omega = ld_c<R>(k.omega), beta = ld_c<R>(k.beta);
+            cx<R> xv[12], sv[12], pv[12], tv[12], vv[12];
             load_spinor<S, true>(a.f[0], Vh, rhs, cb, xv);
             load_spinor<S, true>(a.f[1], Vh, rhs, cb, sv);
             load_spinor<S, true>(a.f[2], Vh, rhs, cb, pv);
             load_spinor<S, true>(a.f[3], Vh, rhs, cb, tv);
-            load_spinor<S, true>(a.f[4], Vh, rhs, cb, hv);
+            load_spinor<S, true>(a.f[4], Vh, rhs, cb, vv);
 #pragma unroll
             for (int e = 0; e < 12; ++e) {
                 xv[e] = xv[e] + alpha * pv[e] + omega * sv[e];
                 sv[e] = sv[e] - omega * tv[e];
-                part[0] += (double)hv[e].re * sv[e].re + (double)hv[e].im * sv[e].im;
-                part[1] += (double)hv[e].re * sv[e].im - (double)hv[e].im * sv[e].re;
-                part[2] += (double)sv[e].re * sv[e].re + (double)sv[e].im * sv[e].im;
+                pv[e] = sv[e] + beta * (pv[e] - omega * vv[e]);
+                part[0] += (double)sv[e].re * sv[e].re + (double)sv[e].im * sv[e].im;
             }
             store_spinor<S, true>(a.f[0], Vh, rhs, cb, xv);
             store_spinor<S, true>(a.f[1], Vh, rhs, cb, sv);
+            store_spinor<S, true>(a.f[2], Vh, rhs, cb, pv);
         }
-        write_parts<3>(part, red, a.parts, rhs, nb, blk);
+        write_parts<1>(part, red, a.parts, rhs, nb, blk);
     } else if constexpr (OP == V_CG_XR) {
         double part[1] = {0};
         if (valid) {
@@ -429,6 +470,41 @@ __global__ __launch_bounds__(BS) void fold_kernel(Segs<VSeg> B)
     });
 }
 
+// f0 (r, precision S) = f1 (the FP64 residual); f2 (p, precision S) += f1 - old f0
+template <typename S>
+__global__ __launch_bounds__(BS) void replace_kernel(Segs<VSeg> B)
+{
+    using R = typename Fmt<S>::R;
+    __shared__ double red[2 * (BS / 64)];
+    for_each_item(B, [&](const VSeg &a, int item) {
+        const int nb = (int)((a.Vh + BS - 1) / BS);
+        const int rhs = item / nb, blk = item - rhs * nb;
+        if (masked_off(a.mask, rhs)) return;
+        count_live(a.live, blk);
+        const int64_t cb = (int64_t)blk * BS + threadIdx.x;
+        double part[2] = {0, 0};
+        if (cb < a.Vh) {
+            cx<R> rv[12], pv[12], hv[12];
+            cx<double> nv[12];
+            load_spinor<S>(a.f[0], a.Vh, rhs, cb, rv);
+            load_spinor<double>(a.f[1], a.Vh, rhs, cb, nv);
+            load_spinor<S>(a.f[2], a.Vh, rhs, cb, pv);
+            load_spinor<S>(a.f[3], a.Vh, rhs, cb, hv);
+#pragma unroll
+            for (int e = 0; e < 12; ++e) {
+                const cx<R> n = {R(nv[e].re), R(nv[e].im)};
+                pv[e] = pv[e] + (n - rv[e]);
+                rv[e] = n;
+                part[0] += (double)hv[e].re * rv[e].re + (double)hv[e].im * rv[e].im;
+                part[1] += (double)hv[e].re * rv[e].im - (double)hv[e].im * rv[e].re;
+            }
+            store_spinor<S, true>(a.f[0], a.Vh, rhs, cb, rv);
+            store_spinor<S, true>(a.f[2], a.Vh, rhs, cb, pv);
+        }
+        write_parts<2>(part, red, a.parts, rhs, nb, blk);
+    });
+}
+
 // f0 = f1 - f2 (FP64)
 __global__ __launch_bounds__(BS) void sub_kernel(Segs<VSeg> B)
 {
@@ -525,6 +601,8 @@ void scalar_launch(int op, const std::vector<SSeg> &segs, const SParams &p, hipS
     case S_BICG_RHO: hipLaunchKernelGGL(scalar_kernel<S_BICG_RHO>, dim3(grid), dim3(64), 0, s, B, p); break;
     case S_BICG_ALPHA: hipLaunchKernelGGL(scalar_kernel<S_BICG_ALPHA>, dim3(grid), dim3(64), 0, s, B, p); break;
     case S_BICG_OMEGA: hipLaunchKernelGGL(scalar_kernel<S_BICG_OMEGA>, dim3(grid), dim3(64), 0, s, B, p); break;
+    case S_BICG_CHECK: hipLaunchKernelGGL(scalar_kernel<S_BICG_CHECK>, dim3(grid), dim3(64), 0, s, B, p); break;
+    case S_BICG_RESYNC: hipLaunchKernelGGL(scalar_kernel<S_BICG_RESYNC>, dim3(grid), dim3(64), 0, s, B, p); break;
     case S_TRUE_RES: hipLaunchKernelGGL(scalar_kernel<S_TRUE_RES>, dim3(grid), dim3(64), 0, s, B, p); break;
     case S_CG_INIT: hipLaunchKernelGGL(scalar_kernel<S_CG_INIT>, dim3(grid), dim3(64), 0, s, B, p); break;
     case S_CG_ALPHA: hipLaunchKernelGGL(scalar_kernel<S_CG_ALPHA>, dim3(grid), dim3(64), 0, s, B, p); break;
@@ -535,16 +613,15 @@ void scalar_launch(int op, const std::vector<SSeg> &segs, const SParams &p, hipS
 
 void vec_launch(int op, int prec, const std::vector<VSeg> &segs, hipStream_t s)
 {
-    static const int nvec[] = {4, 3, 7, 3, 5, 1, 1, 2};
+    static const int nvec[] = {4, 8, 3, 5, 1, 1, 2};
     ProfScope ps(PROF_BLAS, vec_bytes(prec, segs, nvec[op]), s);
     const std::vector<VSeg> sg =
         counted_segs(segs, ps, s, [&](int64_t Vh) { return nvec[op] * field_rhs_bytes(prec, Vh); });
     Segs<VSeg> B = make_segs(sg, vec_items);
     const int grid = grid_for(B.prefix[B.n], PERSIST);
     switch (op) {
-    case V_BICG_P: vec_dispatch<V_BICG_P>(prec, B, grid, s); break;
     case V_BICG_S: vec_dispatch<V_BICG_S>(prec, B, grid, s); break;
-    case V_BICG_XR: vec_dispatch<V_BICG_XR>(prec, B, grid, s); break;
+    case V_BICG_XRP: vec_dispatch<V_BICG_XRP>(prec, B, grid, s); break;
     case V_CG_XR: vec_dispatch<V_CG_XR>(prec, B, grid, s); break;
     case V_CG_P: vec_dispatch<V_CG_P>(prec, B, grid, s); break;
     case V_ZERO: vec_dispatch<V_ZERO>(prec, B, grid, s); break;
@@ -580,6 +657,21 @@ void fold_launch(int prec, const std::vector<VSeg> &segs, hipStream_t s)
     case P32: hipLaunchKernelGGL(fold_kernel<float>, dim3(grid), dim3(BS), 0, s, B); break;
     case P16: hipLaunchKernelGGL(fold_kernel<__half>, dim3(grid), dim3(BS), 0, s, B); break;
     default: hipLaunchKernelGGL(fold_kernel<__hip_bfloat16>, dim3(grid), dim3(BS), 0, s, B); break;
+    }
+}
+
+void replace_launch(int prec, const std::vector<VSeg> &segs, hipStream_t s)
+{
+    ProfScope ps(PROF_BLAS, vec_bytes(P64, segs, 1) + vec_bytes(prec, segs, 5), s);
+    const std::vector<VSeg> sg = counted_segs(
+        segs, ps, s, [&](int64_t Vh) { return field_rhs_bytes(P64, Vh) + 5 * field_rhs_bytes(prec, Vh); });
+    Segs<VSeg> B = make_segs(sg, vec_items);
+    const int grid = grid_for(B.prefix[B.n], PERSIST);
+    switch (prec) {
+    case P64: hipLaunchKernelGGL(replace_kernel<double>, dim3(grid), dim3(BS), 0, s, B); break;
+    case P32: hipLaunchKernelGGL(replace_kernel<float>, dim3(grid), dim3(BS), 0, s, B); break;
+    case P16: hipLaunchKernelGGL(replace_kernel<__half>, dim3(grid), dim3(BS), 0, s, B); break;
+    default: hipLaunchKernelGGL(replace_kernel<__hip_bfloat16>, dim3(grid), dim3(BS), 0, s, B); break;
     }
 }
 

@@ -174,7 +174,7 @@ __device__ __forceinline__ void hop(const DKArgs &a, int64_t nb, int lpar, int64
 template <int EPI>
 constexpr int nparts_c()
 {
-    return EPI == EPI_XPAY_DOT ? 2 : EPI == EPI_XPAY_TS ? 3 : (EPI == EPI_XPAY_NRM || EPI == EPI_XMY_NRM) ? 1 : 0;
+    return EPI == EPI_XPAY_DOT ? 2 : EPI == EPI_XPAY_TS ? 5 : (EPI == EPI_XPAY_NRM || EPI == EPI_XMY_NRM) ? 1 : 0;
 }
 
 // Epilogue for one right-hand side at one site: out = a * acc (PLAIN) or
@@ -216,7 +216,7 @@ __device__ __forceinline__ void epilogue(const DKArgs &a, int rhs, int64_t cb, c
             o[e].re = fma(coef, acc[e].re, xv[e].re);
             o[e].im = fma(coef, acc[e].im, xv[e].im);
         }
-        double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+        double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0, p4 = 0.0;
         if constexpr (EPI == EPI_XPAY_DOT) {
             cx<R> yv[12];
             load_site<S, BUF>(a.y, a.g.Vh, rhs, cb, yv);
@@ -226,11 +226,15 @@ __device__ __forceinline__ void epilogue(const DKArgs &a, int rhs, int64_t cb, c
                 p1 += (double)yv[e].re * o[e].im - (double)yv[e].im * o[e].re;
             }
         } else if constexpr (EPI == EPI_XPAY_TS) {
+            cx<R> yv[12];
+            load_site<S, BUF>(a.y, a.g.Vh, rhs, cb, yv);
 #pragma unroll
             for (int e = 0; e < 12; ++e) {
                 p0 += (double)o[e].re * xv[e].re + (double)o[e].im * xv[e].im;
                 p1 += (double)o[e].re * xv[e].im - (double)o[e].im * xv[e].re;
                 p2 += (double)o[e].re * o[e].re + (double)o[e].im * o[e].im;
+                p3 += (double)yv[e].re * o[e].re + (double)yv[e].im * o[e].im;
+                p4 += (double)yv[e].re * o[e].im - (double)yv[e].im * o[e].re;
             }
         }
         if (valid) {
@@ -241,6 +245,8 @@ __device__ __forceinline__ void epilogue(const DKArgs &a, int rhs, int64_t cb, c
                 part[0] += p0;
                 part[1] += p1;
                 part[2] += p2;
+                part[3] += p3;
+                part[4] += p4;
             }
         }
     }

@@ -156,7 +156,7 @@ enum Epi {
     EPI_PLAIN = 0,     // out = a D in
     EPI_XPAY = 1,      // out = x + a D in
     EPI_XPAY_DOT = 2,  // out = x + a D in; partial (y, out)            [2 doubles]
-    EPI_XPAY_TS = 3,   // out = x + a D in; partials (out, x), |out|^2   [3 doubles]
+    EPI_XPAY_TS = 3,   // out = x + a D in; partials (out, x), |out|^2, (y, out)   [5 doubles]
     EPI_XPAY_NRM = 4,  // out = x + a D in; partial |out|^2              [1 double]
     EPI_XMY_NRM = 5,   // out = x - y + a D in; partial |out|^2          [1 double]
 };
@@ -165,7 +165,7 @@ inline int epi_nparts(int epi)
 {
     switch (epi) {
     case EPI_XPAY_DOT: return 2;
-    case EPI_XPAY_TS: return 3;
+    case EPI_XPAY_TS: return 5;
     case EPI_XPAY_NRM: return 1;
     case EPI_XMY_NRM: return 1;
     default: return 0;
@@ -255,10 +255,14 @@ struct VSeg {
     double *parts = nullptr;    // [nrhs][blas_blocks(Vh)][np] for the reducing operations
     unsigned *live = nullptr;   // profiling: incremented once per right-hand side processed
 };
-enum VOp { V_BICG_P = 0, V_BICG_S, V_BICG_XR, V_CG_XR, V_CG_P, V_ZERO, V_NORM2, V_DOT };
+enum VOp { V_BICG_S = 0, V_BICG_XRP, V_CG_XR, V_CG_P, V_ZERO, V_NORM2, V_DOT };
 void vec_launch(int op, int prec, const std::vector<VSeg> &segs, hipStream_t s);
 void copy_launch(int prec_dst, int prec_src, const std::vector<VSeg> &segs, hipStream_t s);  // f0 = f1
 void fold_launch(int prec, const std::vector<VSeg> &segs, hipStream_t s);   // f0 (FP64) += f1; f1 = 0
+// reliable update of the residual: f0 (r, precision prec) = f1 (FP64 residual), and the search
+// direction f2 (p, precision prec) += f1 - old f0, so that p = r + beta (p - omega v) holds for the
+// replaced r
+void replace_launch(int prec, const std::vector<VSeg> &segs, hipStream_t s);
 void sub_launch(const std::vector<VSeg> &segs, hipStream_t s);              // f0 = f1 - f2 (FP64)
 
 // Operands of a per-right-hand-side scalar kernel for one segment.
@@ -268,18 +272,21 @@ struct SSeg {
     const int *mask = nullptr;
     const double *parts = nullptr, *parts2 = nullptr;
     int nblk = 0;   // site blocks of the producing kernel (partials' middle extent)
+    int nblk2 = 0;  // the same for parts2 where another kernel produced them (0: nblk)
     int nrhs = 0;
     double *out = nullptr;
 };
 struct SParams {
     double tol2 = 0, delta2 = 0;
-    int maxiter = 0, np = 0, first = 0, mixed = 0, final_check = 0;
+    int maxiter = 0, np = 0, mixed = 0, final_check = 0;
 };
 enum SOp {
     S_BICG_INIT = 0,  // parts (+ parts2): |b_e|^2 (+ |b_o|^2)
-    S_BICG_RHO,       // parts: (rhat, r) [, |r|^2]
+    S_BICG_RHO,       // (re)start: parts (rhat, r); rho = (rhat, r), alpha = omega = 1
     S_BICG_ALPHA,     // parts: (rhat, v)
-    S_BICG_OMEGA,     // parts: (t, s), |t|^2
+    S_BICG_OMEGA,     // parts: (t, s), |t|^2, (rhat, t); parts2: (rhat, s): omega, rho, beta
+    S_BICG_CHECK,     // parts: |r|^2: iteration count, convergence and reliable-update flags
+    S_BICG_RESYNC,    // parts: (rhat, r) after a reliable update: rho
     S_TRUE_RES,       // parts (+ parts2): FP64 residual norms
     S_CG_INIT,        // parts: |r|^2
     S_CG_ALPHA,       // parts: (p, q)
