@@ -382,7 +382,7 @@ static void dslash_bytes(const DslashCall &c, double &per_rhs, double &links)
     links = vh * 8.0 * (c.recon == 12 ? 6 : 9) * e;
     int nfield = 2;  // in, out
     if (c.epi != EPI_PLAIN) nfield += 1;                             // x
-    if (c.epi == EPI_XPAY_DOT || c.epi == EPI_XMY_NRM || c.epi == EPI_XPAY_TS) nfield += 1;  // y
+    if (c.epi == EPI_XPAY_DOT || c.epi == EPI_XMY_NRM || c.epi == EPI_XPAY_TS || c.epi == EPI_CG_R) nfield += 1;  // y
     per_rhs = nfield * field;
 }
 
@@ -1328,20 +1328,22 @@ void cgnr_batch(const Ctx &c, double kappa, int iters, SolveWork &w)
     k_zero(P, w.x64.view(), Vh, n, nullptr, c.s);
     k_copy(P, w.p.view(), P, w.r.view(), Vh, n, nullptr, c.s);
     for (int it = 0; it < iters; ++it) {
-        // t = Mhat p ; q = Mhat^+ t with partial (p, q)
+        // t = Mhat p with |t|^2 = (p, Mhat^+ Mhat p); alpha = |r|^2 / |t|^2
         launch_dslash(dcall(c, P, 1, false, EPI_PLAIN, w.p.view(), w.tmpo.view(), NOF, NOF, 1.0, n, nullptr, act),
                       c.s);
-        launch_dslash(
-            dcall(c, P, 0, false, EPI_XPAY, w.tmpo.view(), w.t.view(), w.p.view(), NOF, -k2, n, nullptr, act), c.s);
-        launch_dslash(dcall(c, P, 1, true, EPI_PLAIN, w.t.view(), w.tmpo.view(), NOF, NOF, 1.0, n, nullptr, act), c.s);
         nbd = launch_dslash(
-            dcall(c, P, 0, true, EPI_XPAY_DOT, w.tmpo.view(), w.v.view(), w.t.view(), w.p.view(), -k2, n, parts, act),
-            c.s);
+            dcall(c, P, 0, false, EPI_XPAY_NRM, w.tmpo.view(), w.t.view(), w.p.view(), NOF, -k2, n, parts, act), c.s);
         scalar_launch(S_CG_ALPHA, sseg(nbd), SParams{}, c.s);
-        // r -= alpha q with |r|^2; beta; then x += alpha p and p = r + beta p in one pass (a right-hand
-        // side that finishes in this iteration is flagged 2, so it still takes its x update)
-        vec_launch(V_CG_XR, P, {vs({w.r.view(), w.v.view()}, Vh, n, act, parts, st)}, c.s);
-        scalar_launch(S_CG_BETA, sseg(nb), SParams{}, c.s);
+        // q = Mhat^+ t is formed in the epilogue of the adjoint hop and used there at once:
+        // r -= alpha q with |r|^2 (q is never stored)
+        launch_dslash(dcall(c, P, 1, true, EPI_PLAIN, w.t.view(), w.tmpo.view(), NOF, NOF, 1.0, n, nullptr, act), c.s);
+        DslashCall d4 = dcall(c, P, 0, true, EPI_CG_R, w.tmpo.view(), w.r.view(), w.t.view(), w.r.view(), -k2, n, parts,
+                              act);
+        d4.st = st;
+        nbd = launch_dslash(d4, c.s);
+        // beta; then x += alpha p and p = r + beta p in one pass (a right-hand side that finishes
+        // in this iteration is flagged 2, so it still takes its x update)
+        scalar_launch(S_CG_BETA, sseg(nbd), SParams{}, c.s);
         vec_launch(V_CG_P, P, {vs({w.p.view(), w.r.view(), w.x64.view()}, Vh, n, act, nullptr, st)}, c.s);
     }
     launch_dslash(
@@ -1404,8 +1406,8 @@ struct Stopwatch {
 // half fields in the iteration precision (the p update 4, two plain hops 2
 // each, the hop with the (rhat, v) dot 4, the s update 3, the hop with the
 // (t, s) and |t|^2 sums 3, the x and r update with its sums 7); the truncated
-// CGNR 19 (four hops 2 + 3 + 2 + 4, the r update 3, the fused x and p update
-// 5).  A reliable update moves 8 FP64 half fields (two for the fold, 2 + 4
+// CGNR 16 (four hops 2 + 3 + 2 + 4, the last of them forming q and updating r
+// in its epilogue, and the fused x and p update 5).  A reliable update moves 8 FP64 half fields (two for the fold, 2 + 4
 // for the FP64 residual hops, one for the copy back) and 3 in the iteration
 // precision; the set-up 12 FP64 and 7 iteration-precision half fields
 // (source norms, prepared source, zeroed vectors, the first dot) and the
@@ -1414,7 +1416,7 @@ double solve_bytes(const SolveWork &w, const KState &k, bool cgnr)
 {
     const double vh = (double)w.r.Vh;
     const double fb = vh * (12.0 * elem_bytes(w.prec) + (w.prec == P16 ? 4.0 : 0.0));
-    if (cgnr) return k.iters * 19.0 * fb + 8.0 * fb;
+    if (cgnr) return k.iters * 16.0 * fb + 8.0 * fb;
     const double f8 = vh * 12.0 * 16.0;
     return k.iters * 25.0 * fb + k.updates * (8.0 * f8 + 3.0 * fb) + 15.0 * f8 + 7.0 * fb;
 }

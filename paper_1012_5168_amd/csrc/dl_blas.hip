@@ -220,7 +220,7 @@ __device__ void cg_init(const SSeg &a, const SParams &p, int rhs)
     a.act[rhs] = (rr > 0 && p.maxiter > 0) ? 1 : 0;
 }
 
-// alpha = rr / Re(p, q)
+// alpha = |r|^2 / |Mhat p|^2 (= (p, Mhat^+ Mhat p)), partials [.., 1]
 __device__ void cg_alpha(const SSeg &a, int rhs)
 {
     if (!a.act[rhs]) return;
@@ -228,7 +228,7 @@ __device__ void cg_alpha(const SSeg &a, int rhs)
         if (threadIdx.x == 0) a.act[rhs] = 0;
         return;
     }
-    double pq = sum_parts(a.parts, rhs, a.nblk, 2, 0);
+    double pq = sum_parts(a.parts, rhs, a.nblk, 1, 0);
     if (threadIdx.x != 0) return;
     KState s = a.st[rhs];
     if (pq > 0) {

@@ -32,6 +32,7 @@ struct DKArgs {
     double *partials;
     const int *active;
     unsigned *live_count;
+    const KState *st;
 };
 
 // h = psi_up + s A_mu psi_down (two spin components x three colours) with the
@@ -174,7 +175,10 @@ __device__ __forceinline__ void hop(const DKArgs &a, int64_t nb, int lpar, int64
 template <int EPI>
 constexpr int nparts_c()
 {
-    return EPI == EPI_XPAY_DOT ? 2 : EPI == EPI_XPAY_TS ? 5 : (EPI == EPI_XPAY_NRM || EPI == EPI_XMY_NRM) ? 1 : 0;
+    return EPI == EPI_XPAY_DOT ? 2
+           : EPI == EPI_XPAY_TS ? 5
+           : (EPI == EPI_XPAY_NRM || EPI == EPI_XMY_NRM || EPI == EPI_CG_R) ? 1
+                                                                           : 0;
 }
 
 // Epilogue for one right-hand side at one site: out = a * acc (PLAIN) or
@@ -237,6 +241,17 @@ __device__ __forceinline__ void epilogue(const DKArgs &a, int rhs, int64_t cb, c
                 p4 += (double)yv[e].re * o[e].im - (double)yv[e].im * o[e].re;
             }
         }
+        if constexpr (EPI == EPI_CG_R) {
+            // the residual update of the normal equations' CG: r -= alpha q
+            const R al = R(a.st[rhs].alpha[0]);
+            cx<R> yv[12];
+            load_site<S, BUF>(a.y, a.g.Vh, rhs, cb, yv);
+#pragma unroll
+            for (int e = 0; e < 12; ++e) {
+                o[e].re = fma(-al, o[e].re, yv[e].re);
+                o[e].im = fma(-al, o[e].im, yv[e].im);
+            }
+        }
         if (valid) {
             if constexpr (EPI == EPI_XPAY_DOT) {
                 part[0] += p0;
@@ -250,7 +265,7 @@ __device__ __forceinline__ void epilogue(const DKArgs &a, int rhs, int64_t cb, c
             }
         }
     }
-    if constexpr (EPI == EPI_XPAY_NRM || EPI == EPI_XMY_NRM) {
+    if constexpr (EPI == EPI_XPAY_NRM || EPI == EPI_XMY_NRM || EPI == EPI_CG_R) {
         double p0 = 0.0;
 #pragma unroll
         for (int e = 0; e < 12; ++e) p0 += (double)o[e].re * o[e].re + (double)o[e].im * o[e].im;

@@ -50,6 +50,9 @@ static void dslash_go_epi(const Segs<DKArgs> &B, int epi, int kind, int nr, int 
     case EPI_XPAY_TS: dslash_go_nr<S, NE, DAG, EPI_XPAY_TS>(B, kind, nr, grid, bs, rb, s); break;
     case EPI_XPAY_NRM: dslash_go_nr<S, NE, DAG, EPI_XPAY_NRM>(B, kind, nr, grid, bs, rb, s); break;
     case EPI_XMY_NRM: dslash_go_nr<S, NE, DAG, EPI_XMY_NRM>(B, kind, nr, grid, bs, rb, s); break;
+    case EPI_CG_R:  // only the adjoint hop of the normal equations uses it
+        if constexpr (DAG) dslash_go_nr<S, NE, DAG, EPI_CG_R>(B, kind, nr, grid, bs, rb, s);
+        break;
     default: break;
     }
 }
@@ -106,6 +109,7 @@ void launch_dslash_t(const DslashCall *c, int nseg, int kind, int nr, int bs, in
         a.partials = c[k].partials;
         a.active = c[k].active;
         a.live_count = c[k].live_count;
+        a.st = c[k].st;
         const int groups = kind == 1 ? 1 : (c[k].nrhs + nr - 1) / nr;
         B.prefix[k + 1] = B.prefix[k] + a.nblk * groups;
     }

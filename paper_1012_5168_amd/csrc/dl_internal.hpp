@@ -159,6 +159,8 @@ enum Epi {
     EPI_XPAY_TS = 3,   // out = x + a D in; partials (out, x), |out|^2, (y, out)   [5 doubles]
     EPI_XPAY_NRM = 4,  // out = x + a D in; partial |out|^2              [1 double]
     EPI_XMY_NRM = 5,   // out = x - y + a D in; partial |out|^2          [1 double]
+    EPI_CG_R = 6,      // q = x + a D in; out = y - alpha q (out = y in place, alpha from
+                       // the solver state); partial |out|^2; q itself is not stored   [1 double]
 };
 
 inline int epi_nparts(int epi)
@@ -168,6 +170,7 @@ inline int epi_nparts(int epi)
     case EPI_XPAY_TS: return 5;
     case EPI_XPAY_NRM: return 1;
     case EPI_XMY_NRM: return 1;
+    case EPI_CG_R: return 1;
     default: return 0;
     }
 }
@@ -186,6 +189,7 @@ struct DslashCall {
     double *partials;     // [nrhs][nblk][nparts] (epilogues with reductions)
     const int *active;    // per right-hand side flag or null
     unsigned *live_count = nullptr;  // profiling: live right-hand-side blocks
+    const struct KState *st = nullptr;  // per right-hand side solver state (EPI_CG_R's alpha)
 };
 
 // launch with the tuned (or default) configuration; returns the number of
@@ -289,7 +293,7 @@ enum SOp {
     S_BICG_RESYNC,    // parts: (rhat, r) after a reliable update: rho
     S_TRUE_RES,       // parts (+ parts2): FP64 residual norms
     S_CG_INIT,        // parts: |r|^2
-    S_CG_ALPHA,       // parts: (p, q)
+    S_CG_ALPHA,       // parts: |Mhat p|^2
     S_CG_BETA,        // parts: |r|^2
     S_SUM             // out[rhs * np + k] = sum of partials
 };

@@ -15,8 +15,10 @@
 // wavefronts per SIMD (0: as compiled) and regions of `grid` blocks.  The
 // first time a (precision, link format, adjoint, epilogue, right-hand sides,
 // lattices) combination is launched, each candidate is timed with HIP events
-// on the real operands (every hopping launch is idempotent: its output never
-// aliases an input); a candidate replaces the default only if it is 3%
+// on the real operands (a hopping launch is idempotent when its output
+// aliases no input; the one that updates its y operand in place is timed
+// with its output redirected to a scratch field of the same size); a
+// candidate replaces the default only if it is 3%
 // faster, and the result is kept in memory and in a text cache file
 // (DL_TUNE_CACHE, default ~/.cache/dloops/tune_gfx950_v4.txt).
 // DL_TUNE=0 disables tuning and uses the default: the LDS-link kernel with 2
@@ -149,7 +151,15 @@ void save_locked(const Key &k, const TuneChoice &t)
 bool aliases(const std::vector<DslashCall> &cs)
 {
     for (const DslashCall &c : cs)
-        if (c.out.d == c.in.d || (c.x.d && c.out.d == c.x.d) || (c.y.d && c.out.d == c.y.d)) return true;
+        if (c.out.d == c.in.d || (c.x.d && c.out.d == c.x.d)) return true;
+    return false;
+}
+
+// calls that write their y operand in place
+bool in_place(const std::vector<DslashCall> &cs)
+{
+    for (const DslashCall &c : cs)
+        if (c.y.d && c.out.d == c.y.d) return true;
     return false;
 }
 
@@ -193,6 +203,23 @@ TuneChoice tune_lookup(const std::vector<DslashCall> &c, hipStream_t s)
     float best_ms = 1e30f;
     std::vector<DslashCall> t = c;
     for (DslashCall &d : t) d.live_count = nullptr;
+    // in-place calls: candidates write a scratch field instead
+    std::vector<DevBuf> scratch;
+    if (in_place(c)) {
+        try {
+            for (DslashCall &d : t) {
+                const size_t data = (size_t)d.nrhs * 12 * (size_t)d.g.Vh * elem_bytes(d.prec);
+                const size_t nrm = d.prec == P16 ? (size_t)d.nrhs * (size_t)d.g.Vh * sizeof(float) : 0;
+                scratch.emplace_back(data + nrm);
+                d.out.d = scratch.back().p;
+                d.out.nrm = nrm ? reinterpret_cast<float *>(static_cast<char *>(scratch.back().p) + data) : nullptr;
+            }
+        } catch (...) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return dflt;
+        }
+    }
     std::vector<TuneChoice> cands{dflt};
     for (const TuneChoice &cand : candidates(c[0].prec, c[0].recon))
         if (!(cand.kind == dflt.kind && cand.nr == dflt.nr && cand.bs == dflt.bs && cand.persistent == dflt.persistent))
