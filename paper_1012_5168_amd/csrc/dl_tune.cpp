@@ -22,11 +22,12 @@
 // faster, and the result is kept in memory and in a text cache file
 // (DL_TUNE_CACHE, default ~/.cache/dloops/tune_gfx950_v4.txt).
 // DL_TUNE=0 disables tuning and uses the default: the LDS-link kernel with 2
-// wavefronts, one wavefront per SIMD and regions of 64 blocks where its links
-// fit in LDS, else the item kernel with 1 right-hand side per thread and 256
-// sites per workgroup; DL_TUNE=item and DL_TUNE=lds pin those two choices (the
-// latter where the LDS-link kernel applies); DL_TUNE=cfg:kind:nr:bs:grid pins
-// one candidate of the list below (ignored where it is not a candidate).  The
+// wavefronts, one wavefront per SIMD (for FP64 the LDS alone enforces it) and
+// regions of 64 blocks where its links fit in LDS, else the item kernel with
+// 1 right-hand side per thread and 256 sites per workgroup; DL_TUNE=item and
+// DL_TUNE=lds pin those two choices (the latter where the LDS-link kernel
+// applies); DL_TUNE=cfg:kind:nr:bs:grid pins one configuration the launcher
+// runs (ignored where it cannot run: see launchable below).  The
 // variable is read at every lookup.  Tuning never runs while the stream is
 // being captured.
 #include <hip/hip_runtime.h>
@@ -93,7 +94,16 @@ int tune_mode(TuneChoice *pin = nullptr)
     return 0;
 }
 
-// the candidate set; a cached choice outside it is ignored
+// wavefronts per SIMD that the LDS-link kernel's LDS allows with `lanes`
+// wavefronts per workgroup (a CU has four SIMDs and LDS_WORKGROUP_BYTES of LDS)
+int lds_waves_per_simd(int prec, int recon, int lanes)
+{
+    return LDS_WORKGROUP_BYTES / lds_link_block_bytes(prec, recon) * lanes / 4;
+}
+
+// The candidate set; a cached choice outside it is ignored.  An occupancy cap
+// that the LDS already enforces (the FP64 links of a block take 72 KiB, so
+// two wavefronts per block are one per SIMD) is no separate candidate.
 std::vector<TuneChoice> candidates(int prec, int recon)
 {
     std::vector<TuneChoice> v;
@@ -103,7 +113,8 @@ std::vector<TuneChoice> candidates(int prec, int recon)
     if (dslash_lds_ok(prec, recon))
         for (int lanes : {1, 2, 4})
             for (int occ : {0, 1, 2})
-                for (int rb : {32, 64, 128}) v.push_back(TuneChoice{1, lanes, occ, rb});
+                if (occ == 0 || lds_waves_per_simd(prec, recon, lanes) > occ)
+                    for (int rb : {32, 64, 128}) v.push_back(TuneChoice{1, lanes, occ, rb});
     return v;
 }
 
@@ -114,9 +125,18 @@ bool valid_choice(const TuneChoice &t, int prec, int recon)
     return false;
 }
 
+// a configuration the launcher runs (DL_TUNE=cfg:... may pin any of them)
+bool launchable(const TuneChoice &t, int prec, int recon)
+{
+    if (t.kind == 0) return (t.nr == 1 || t.nr == 2) && (t.bs == 64 || t.bs == 128 || t.bs == 256) && t.persistent >= 0;
+    return t.kind == 1 && dslash_lds_ok(prec, recon) && (t.nr == 1 || t.nr == 2 || t.nr == 4) && t.bs >= 0 &&
+           t.bs <= 2 && t.persistent > 0;
+}
+
 TuneChoice default_choice(int prec, int recon)
 {
-    return dslash_lds_ok(prec, recon) ? TuneChoice{1, 2, 1, 64} : TuneChoice{0, 1, 256, 0};
+    if (!dslash_lds_ok(prec, recon)) return TuneChoice{0, 1, 256, 0};
+    return TuneChoice{1, 2, lds_waves_per_simd(prec, recon, 2) > 1 ? 1 : 0, 64};
 }
 
 void load_locked()
@@ -170,7 +190,7 @@ TuneChoice tune_lookup(const std::vector<DslashCall> &c, hipStream_t s)
     const TuneChoice dflt = default_choice(c[0].prec, c[0].recon);
     TuneChoice pin;
     const int mode = tune_mode(&pin);
-    if (mode == 5 && valid_choice(pin, c[0].prec, c[0].recon)) return pin;
+    if (mode == 5 && launchable(pin, c[0].prec, c[0].recon)) return pin;
     if (mode == 2) return TuneChoice{0, 1, 256, 0};
     if (mode == 1 || mode == 3 || aliases(c)) return dflt;
     const Key k = make_key(c);
