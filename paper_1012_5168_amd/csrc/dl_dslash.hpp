@@ -434,6 +434,26 @@ constexpr bool lds_pipelined()
     return !std::is_same<S, float>::value;
 }
 
+// How many hops ahead the pipelined walk issues its neighbour loads (1 or 2;
+// it keeps 2 x that many neighbour buffers).  Two: measured at 288
+// right-hand sides on 16^3 x 32, FP64 1868 -> 1842 us and BF16 636 -> 627 us
+// per plain launch (FP64 246 registers, still one wavefront per SIMD; FP16 127,
+// still four, and unchanged in time).
+#ifndef LDS_PREFETCH
+#define LDS_PREFETCH 2
+#endif
+template <typename S>
+constexpr int lds_prefetch()
+{
+    return LDS_PREFETCH;
+}
+
+// a neighbour spinor converted to the arithmetic precision
+template <typename R>
+struct CxSpinor {
+    cx<R> v[12];
+};
+
 // the per-(right-hand side, site block) partial sums of a reducing epilogue,
 // summed over the wavefront and written by its first lane
 template <int NP>
@@ -524,6 +544,30 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
 
         const R bf = (g.tap && s.t + 1 == g.T) ? R(-1) : R(1);
         const R bb = (g.tap && s.t == 0) ? R(-1) : R(1);
+        // hop d's neighbour of right-hand side rr (resource rs) into dst
+        auto load_hop = [&](__amdgpu_buffer_rsrc_t rs, int rr, int d, CxSpinor<R> &dst) {
+            if (d < 6)
+                load_spinor_rsrc<S>(rs, a.in, g.Vh, rr, nb[d], dst.v);
+            else if (d == 6)
+                load_half_rsrc<S, t_half<SF>()>(rs, a.in, g.Vh, rr, nb[6], dst.v);
+            else
+                load_half_rsrc<S, t_half<SB>()>(rs, a.in, g.Vh, rr, nb[7], dst.v);
+        };
+        // hop d on a loaded neighbour, with its link from LDS
+        auto apply_hop = [&](int d, const CxSpinor<R> &src, cx<R> acc[12]) {
+            cx<R> u[9];
+            load_u(d, sl, u);
+            switch (d) {
+            case 0: hop_mul<R, 0, SF, true>(u, src.v, acc); break;
+            case 1: hop_mul<R, 0, SB, false>(u, src.v, acc); break;
+            case 2: hop_mul<R, 1, SF, true>(u, src.v, acc); break;
+            case 3: hop_mul<R, 1, SB, false>(u, src.v, acc); break;
+            case 4: hop_mul<R, 2, SF, true>(u, src.v, acc); break;
+            case 5: hop_mul<R, 2, SB, false>(u, src.v, acc); break;
+            case 6: hop_mul_t<R, SF, true>(u, src.v, R(2) * bf, acc); break;
+            default: hop_mul_t<R, SB, false>(u, src.v, R(2) * bb, acc); break;
+            }
+        };
         unsigned nlive = 0;
         // Wavefront w takes right-hand sides w, w + LANES, ...  The flags of its
         // next 64 are read once, one per lane, into a wave-uniform mask, so the
@@ -535,28 +579,25 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
             uint64_t m = __ballot(on);
             nlive += (unsigned)__popcll(m);
             if constexpr (lds_pipelined<S>()) {
-                // Neighbour spinors double-buffered: hop d + 1's loads are in
-                // flight while hop d computes, and the next right-hand side's
-                // first hop while the last hop and the epilogue of this one
-                // run.  The empty asm statements fence memory operations: the
-                // one after a hop's loads keeps them ahead of the previous
-                // hop's arithmetic, the accumulator pin after that arithmetic
-                // keeps the following loads behind it (without the fences the
-                // compiler issues all eight hops' loads at once and spills).
+                // Neighbour spinors prefetched PF hops ahead: hop d + PF's
+                // loads are in flight while hop d computes, and the next
+                // right-hand side's first hops while the last hops and the
+                // epilogue of this one run.  The empty asm statements fence
+                // memory operations: the one after a hop's loads keeps them
+                // ahead of the previous hop's arithmetic, the accumulator pin
+                // after that arithmetic keeps the following loads behind it
+                // (without the fences the compiler issues all eight hops'
+                // loads at once and spills).
                 if (m == 0) continue;
                 int r = r0 + __builtin_ctzll(m) * LANES;
                 m &= m - 1;
                 __amdgpu_buffer_rsrc_t rin = spinor_rsrc<S>(a.in, g.Vh, r);
-                cx<R> pa[12], pb[12];
-                auto load_hop = [&](__amdgpu_buffer_rsrc_t rs, int rr, int d, cx<R> *dst) {
-                    if (d < 6)
-                        load_spinor_rsrc<S>(rs, a.in, g.Vh, rr, nb[d], dst);
-                    else if (d == 6)
-                        load_half_rsrc<S, t_half<SF>()>(rs, a.in, g.Vh, rr, nb[6], dst);
-                    else
-                        load_half_rsrc<S, t_half<SB>()>(rs, a.in, g.Vh, rr, nb[7], dst);
-                };
-                load_hop(rin, r, 0, pa);
+                // hop k's neighbour goes to buf[k % NBUF]: NBUF divides 8, so
+                // the assignment is the same for every right-hand side
+                constexpr int PF = lds_prefetch<S>(), NBUF = 2 * PF;
+                CxSpinor<R> buf[NBUF];
+#pragma unroll
+                for (int k = 0; k < PF; ++k) load_hop(rin, r, k, buf[k]);
                 while (true) {
                     const bool more = m != 0;
                     const int rn = more ? r0 + __builtin_ctzll(m) * LANES : r;
@@ -570,27 +611,18 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
                     for (int e = 0; e < 12; ++e) acc[e] = {R(0), R(0)};
 #pragma unroll
                     for (int d = 0; d < 8; ++d) {
-                        cx<R> *cur = (d & 1) ? pb : pa;
-                        // after the last right-hand side rn = r: the redundant
-                        // loads keep the issue unconditional, so the compiler
-                        // need not wait for them before this hop's arithmetic
-                        if (d + 1 < 8)
-                            load_hop(rin, r, d + 1, (d & 1) ? pa : pb);
+                        // hop d + PF's loads (the next right-hand side's first
+                        // hops near the end; after the last right-hand side
+                        // rn = r: the redundant loads keep the issue
+                        // unconditional, so the compiler need not wait for
+                        // them before this hop's arithmetic)
+                        const int t = d + PF;
+                        if (t < 8)
+                            load_hop(rin, r, t, buf[t % NBUF]);
                         else
-                            load_hop(rin_n, rn, 0, pa);
+                            load_hop(rin_n, rn, t - 8, buf[t % NBUF]);
                         asm volatile("" ::: "memory");
-                        cx<R> u[9];
-                        load_u(d, sl, u);
-                        switch (d) {
-                        case 0: hop_mul<R, 0, SF, true>(u, cur, acc); break;
-                        case 1: hop_mul<R, 0, SB, false>(u, cur, acc); break;
-                        case 2: hop_mul<R, 1, SF, true>(u, cur, acc); break;
-                        case 3: hop_mul<R, 1, SB, false>(u, cur, acc); break;
-                        case 4: hop_mul<R, 2, SF, true>(u, cur, acc); break;
-                        case 5: hop_mul<R, 2, SB, false>(u, cur, acc); break;
-                        case 6: hop_mul_t<R, SF, true>(u, cur, R(2) * bf, acc); break;
-                        default: hop_mul_t<R, SB, false>(u, cur, R(2) * bb, acc); break;
-                        }
+                        apply_hop(d, buf[d % NBUF], acc);
                         pin_acc<R>(acc);
                     }
                     epilogue<S, EPI, true, true>(a, r, cb, acc, part, valid);
@@ -612,28 +644,9 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
                     for (int e = 0; e < 12; ++e) acc[e] = {R(0), R(0)};
 #pragma unroll
                     for (int d = 0; d < 8; ++d) {
-                        cx<R> u[9];
-                        load_u(d, sl, u);
-                        if (d < 6) {
-                            cx<R> psi[12];
-                            load_spinor_rsrc<S>(rin, a.in, g.Vh, r, nb[d], psi);
-                            switch (d) {
-                            case 0: hop_mul<R, 0, SF, true>(u, psi, acc); break;
-                            case 1: hop_mul<R, 0, SB, false>(u, psi, acc); break;
-                            case 2: hop_mul<R, 1, SF, true>(u, psi, acc); break;
-                            case 3: hop_mul<R, 1, SB, false>(u, psi, acc); break;
-                            case 4: hop_mul<R, 2, SF, true>(u, psi, acc); break;
-                            default: hop_mul<R, 2, SB, false>(u, psi, acc); break;
-                            }
-                        } else if (d == 6) {
-                            cx<R> half[6];
-                            load_half_rsrc<S, t_half<SF>()>(rin, a.in, g.Vh, r, nb[d], half);
-                            hop_mul_t<R, SF, true>(u, half, R(2) * bf, acc);
-                        } else {
-                            cx<R> half[6];
-                            load_half_rsrc<S, t_half<SB>()>(rin, a.in, g.Vh, r, nb[d], half);
-                            hop_mul_t<R, SB, false>(u, half, R(2) * bb, acc);
-                        }
+                        CxSpinor<R> cur;
+                        load_hop(rin, r, d, cur);
+                        apply_hop(d, cur, acc);
                         pin_acc<R>(acc);
                     }
                     epilogue<S, EPI, true, true>(a, r, cb, acc, part, valid);
