@@ -435,17 +435,19 @@ constexpr bool lds_pipelined()
 }
 
 // How many hops ahead the pipelined walk issues its neighbour loads (1 or 2;
-// it keeps 2 x that many neighbour buffers).  Two: measured at 288
-// right-hand sides on 16^3 x 32, FP64 1868 -> 1842 us and BF16 636 -> 627 us
-// per plain launch (FP64 246 registers, still one wavefront per SIMD; FP16 127,
-// still four, and unchanged in time).
+// it keeps 2 x that many neighbour buffers).  Measured at 288 right-hand
+// sides on 16^3 x 32: two hops ahead speed the plain FP64 launch up from 1868
+// to 1842 us and the plain BF16 one from 636 to 627 us; FP16 is unchanged,
+// and the FP64 epilogue variants slow down (x + a D in with a dot product
+// 2624 -> 3006 us: 250 registers instead of 220), so only the plain FP64 and
+// BF16 launches take two.  LDS_PREFETCH=1 builds every variant with one.
 #ifndef LDS_PREFETCH
 #define LDS_PREFETCH 2
 #endif
-template <typename S>
+template <typename S, int EPI>
 constexpr int lds_prefetch()
 {
-    return LDS_PREFETCH;
+    return (EPI == EPI_PLAIN && !std::is_same<S, __half>::value) ? LDS_PREFETCH : 1;
 }
 
 // a neighbour spinor converted to the arithmetic precision
@@ -594,7 +596,7 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
                 __amdgpu_buffer_rsrc_t rin = spinor_rsrc<S>(a.in, g.Vh, r);
                 // hop k's neighbour goes to buf[k % NBUF]: NBUF divides 8, so
                 // the assignment is the same for every right-hand side
-                constexpr int PF = lds_prefetch<S>(), NBUF = 2 * PF;
+                constexpr int PF = lds_prefetch<S, EPI>(), NBUF = 2 * PF;
                 CxSpinor<R> buf[NBUF];
 #pragma unroll
                 for (int k = 0; k < PF; ++k) load_hop(rin, r, k, buf[k]);
