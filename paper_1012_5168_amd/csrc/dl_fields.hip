@@ -399,46 +399,49 @@ __device__ __forceinline__ void grad_dir(const Field &se, const Field &so, const
     }
 }
 
-// grad[mu][x] += kappa b_mu(x) sum_rhs (conj X + Y^T); one thread per site,
-// every (mu, site) entry owned by exactly one thread
-__global__ __launch_bounds__(BS) void link_grad_kernel(Field se, Field so, Field ae, Field ao, Geom g, int nrhs,
-                                                       double kappa, double *grad)
+// grad[mu][x] += kappa b_mu(x) sum_rhs (conj X + Y^T).  A workgroup takes 64
+// sites of one parity and its four wavefronts the four directions (wavefront
+// mu owns the entries (mu, x) of those sites), so the four walk the
+// right-hand sides together and read each site's own spinors at about the
+// same time: one fetch from memory serves all four instead of one pass over
+// every right-hand side per direction.
+__global__ __launch_bounds__(256) void link_grad_kernel(Field se, Field so, Field ae, Field ao, Geom g, int nrhs,
+                                                        double kappa, double *grad)
 {
     const int par = blockIdx.y;
-    const int cb = blockIdx.x * BS + threadIdx.x;
+    const int mu = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int cb = blockIdx.x * 64 + (threadIdx.x & 63);
     if (cb >= g.Vh) return;
     const Site s = decode(g, cb, par);
     const int64_t lex = lex_index(g, s);
     const int64_t V = 2 * (int64_t)g.Vh;
     const int64_t base_x = cb - (s.x >> 1);
-    for (int mu = 0; mu < 4; ++mu) {
-        cx<double> acc[9];
+    cx<double> acc[9];
 #pragma unroll
-        for (int e = 0; e < 9; ++e) acc[e] = {0.0, 0.0};
-        int64_t cby;
-        double b = 1.0;
-        if (mu == 0) {
-            const int xf = s.x + 1 == g.X ? 0 : s.x + 1;
-            cby = base_x + (xf >> 1);
-            grad_dir<0>(se, so, ae, ao, g, par, cb, cby, nrhs, acc);
-        } else if (mu == 1) {
-            cby = s.y + 1 == g.Y ? cb - (int64_t)(g.Y - 1) * g.sY : cb + g.sY;
-            grad_dir<1>(se, so, ae, ao, g, par, cb, cby, nrhs, acc);
-        } else if (mu == 2) {
-            cby = s.z + 1 == g.Z ? cb - (int64_t)(g.Z - 1) * g.sZ : cb + g.sZ;
-            grad_dir<2>(se, so, ae, ao, g, par, cb, cby, nrhs, acc);
-        } else {
-            cby = s.t + 1 == g.T ? cb - (int64_t)(g.T - 1) * g.sT : cb + g.sT;
-            if (g.tap && s.t + 1 == g.T) b = -1.0;
-            grad_dir<3>(se, so, ae, ao, g, par, cb, cby, nrhs, acc);
-        }
-        double2 *dst = reinterpret_cast<double2 *>(grad) + ((int64_t)mu * V + lex) * 9;
-        const double f = kappa * b;
+    for (int e = 0; e < 9; ++e) acc[e] = {0.0, 0.0};
+    int64_t cby;
+    double b = 1.0;
+    if (mu == 0) {
+        const int xf = s.x + 1 == g.X ? 0 : s.x + 1;
+        cby = base_x + (xf >> 1);
+        grad_dir<0>(se, so, ae, ao, g, par, cb, cby, nrhs, acc);
+    } else if (mu == 1) {
+        cby = s.y + 1 == g.Y ? cb - (int64_t)(g.Y - 1) * g.sY : cb + g.sY;
+        grad_dir<1>(se, so, ae, ao, g, par, cb, cby, nrhs, acc);
+    } else if (mu == 2) {
+        cby = s.z + 1 == g.Z ? cb - (int64_t)(g.Z - 1) * g.sZ : cb + g.sZ;
+        grad_dir<2>(se, so, ae, ao, g, par, cb, cby, nrhs, acc);
+    } else {
+        cby = s.t + 1 == g.T ? cb - (int64_t)(g.T - 1) * g.sT : cb + g.sT;
+        if (g.tap && s.t + 1 == g.T) b = -1.0;
+        grad_dir<3>(se, so, ae, ao, g, par, cb, cby, nrhs, acc);
+    }
+    double2 *dst = reinterpret_cast<double2 *>(grad) + ((int64_t)mu * V + lex) * 9;
+    const double f = kappa * b;
 #pragma unroll
-        for (int e = 0; e < 9; ++e) {
-            double2 o = dst[e];
-            dst[e] = make_double2(o.x + f * acc[e].re, o.y + f * acc[e].im);
-        }
+    for (int e = 0; e < 9; ++e) {
+        double2 o = dst[e];
+        dst[e] = make_double2(o.x + f * acc[e].re, o.y + f * acc[e].im);
     }
 }
 
@@ -581,8 +584,9 @@ void k_link_grad(Field se, Field so, Field ae, Field ao, const Geom &g, int nrhs
                  hipStream_t s)
 {
     ProfScope ps(PROF_TRACE, 4 * field_bytes(P64, g.Vh, nrhs) + 2.0 * 2 * g.Vh * 4 * 9 * 16, s);
-    dim3 grid((g.Vh + BS - 1) / BS, 2);
-    hipLaunchKernelGGL(link_grad_kernel, grid, dim3(BS), 0, s, se, so, ae, ao, g, nrhs, kappa, grad);
+    // 64 sites and four directions (one wavefront each) per workgroup
+    dim3 grid((g.Vh + 63) / 64, 2);
+    hipLaunchKernelGGL(link_grad_kernel, grid, dim3(256), 0, s, se, so, ae, ao, g, nrhs, kappa, grad);
 }
 
 void k_links_reorder(const double *canon, double *dst, const Geom &g, hipStream_t s)
