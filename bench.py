@@ -403,10 +403,10 @@ def synth_workload(name):
 
 # Memory-side bytes per launch of the plain FP64 hopping kernel, from the two
 # rocprofv3 counter runs of profiles/dslash_plain_f64_16x16x16x32_288rhs.md
-# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, KiB -> bytes, mean over the 116
-# dispatches of warm-up + one step), keyed by the launch configuration they
-# were taken with.  Another configuration reports null.
-PROFILED_TRAFFIC = {(1, 2, 1, 64): 9.96e9, (1, 2, 1, 128): 9.84e9}
+# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, KiB -> bytes, mean over the 174
+# dispatches of the warm-up, timed and unprofiled steps), keyed by the launch
+# configuration they were taken with.  Another configuration reports null.
+PROFILED_TRAFFIC = {(1, 2, 0, 64): 8.40e9}
 
 
 def kernel_name(cfg):
