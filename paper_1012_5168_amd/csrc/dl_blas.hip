@@ -94,8 +94,8 @@ __device__ void bicg_rho(const SSeg &a, const SParams &p, int rhs)
 
 // After the x / r / p update of an iteration: |r|^2 from partials [.., 1];
 // counts the iteration and flags convergence (or the iteration cap, or a
-// breakdown rho = 0) for the FP64 true-residual check, and a reliable update
-// when |r| fell by delta since the last one.
+// breakdown: rho = 0 or omega = 0) for the FP64 true-residual check, and a
+// reliable update when |r| fell by delta since the last one.
 __device__ void bicg_check(const SSeg &a, const SParams &p, int rhs)
 {
     if (!a.act[rhs]) return;
@@ -109,7 +109,8 @@ __device__ void bicg_check(const SSeg &a, const SParams &p, int rhs)
         a.act[rhs] = 0;
         a.upd[rhs] = 0;
     } else {
-        if (rr <= s.stop2 || s.iters >= s.maxiter || (s.rho[0] == 0 && s.rho[1] == 0)) {
+        if (rr <= s.stop2 || s.iters >= s.maxiter || (s.rho[0] == 0 && s.rho[1] == 0) ||
+            (s.omega[0] == 0 && s.omega[1] == 0)) {
             // converged (or out of iterations, or breakdown): check the FP64 true residual
             a.act[rhs] = 0;
             a.upd[rhs] = 1;
@@ -137,6 +138,9 @@ __device__ void bicg_alpha(const SSeg &a, int rhs)
 // rho' = (rhat, s) - omega (rhat, t), with (rhat, s) from parts2 [.., 2] (the
 // s update); beta = (rho' / rho) (alpha / omega).  Each dot is taken directly
 // from the vectors of this iteration: nothing accumulates across iterations.
+// omega = 0 (t = 0, e.g. s = 0 after an exact half step) ends the recursion:
+// beta is set to 0, and the check sends the right-hand side to the FP64 true
+// residual, which either confirms convergence or restarts from it.
 __device__ void bicg_omega(const SSeg &a, int rhs)
 {
     if (!a.act[rhs]) return;
@@ -157,9 +161,13 @@ __device__ void bicg_omega(const SSeg &a, int rhs)
     cmul(s.omega, rt, wrt);
     rn[0] = rs[0] - wrt[0];
     rn[1] = rs[1] - wrt[1];
-    cdiv(rn, s.rho, q);
-    cdiv(s.alpha, s.omega, ao);
-    cmul(q, ao, s.beta);
+    if (s.omega[0] == 0 && s.omega[1] == 0) {
+        s.beta[0] = s.beta[1] = 0.0;
+    } else {
+        cdiv(rn, s.rho, q);
+        cdiv(s.alpha, s.omega, ao);
+        cmul(q, ao, s.beta);
+    }
     s.rho[0] = rn[0];
     s.rho[1] = rn[1];
     a.st[rhs] = s;

@@ -262,6 +262,35 @@ def test_full_size_loops_batch_properties(dl, dev):
     assert np.max(np.abs(L.imag)) > 1e-3  # per timeslice the imaginary parts do not vanish
 
 
+def test_kappa_zero_solves_in_one_step(dl, dev):
+    """kappa = 0 (M = 1): BiCGStab reaches x = b exactly in its first half step, where s = 0 makes
+    t = 0 and omega = 0; the recursion must stop there and report the solve as converged (FP64 in
+    one iteration; FP32 with FP64 reliable updates in a few, since its iterate holds b only to FP32
+    rounding and the FP64 true residual restarts it), as the oracle's BiCGStab does, and the loops
+    must equal the oracle's (Tr Gamma eta eta^+ summed per timeslice); the truncated CGNR gives
+    x = b too."""
+    dims = (4, 4, 4, 6)
+    U = synth.gauge_field(dims, 0.5, seed=393)
+    G = dl.Gauge(dl.Lattice(dims, 1), U, precs=(dl.DL_F64, dl.DL_F32))
+    b = synth.random_spinor(dims, 3, seed=394)
+    for prm in (dl.solve_params(tol=1e-12, maxiter=50), dl.solve_params(prec=dl.DL_F32, tol=1e-10, maxiter=50)):
+        x, st = dl.solve(G, 0.0, to_dev(b, dev), prm)
+        x = from_dev(x)
+        for r in range(3):
+            assert st[r][0] == dl.DL_OK and st[r][1] <= (1 if prm.prec == dl.DL_F64 else 3), (prm.prec, r, st[r])
+            assert np.linalg.norm(x[r] - b[r]) <= 1e-6 * np.linalg.norm(b[r]), (prm.prec, r)
+    x, st = dl.solve(G, 0.0, to_dev(b, dev), dl.solve_params(solver=dl.DL_CGNR, prec=dl.DL_F64, fixed_iters=25))
+    x = from_dev(x)
+    assert all(s[0] == dl.DL_OK for s in st)
+    assert np.max(np.abs(x - b)) <= 1e-14 * np.max(np.abs(b))
+    gam = [0, 15]
+    L, st = dl.loops(G, 0.0, dl.z2_sources(395, 2, scheme=dl.DL_DIL_SPIN_COLOUR), gam,
+                     dl.solve_params(tol=1e-12, maxiter=50))
+    assert all(s[0] == dl.DL_OK for s in st), st
+    ref = oracle.loops_z2(U, dims, 0.0, 395, range(2), oracle.SCHEME_SPIN_COLOUR, gam, tol=1e-13)
+    assert np.max(np.abs(L - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
 def test_zero_and_empty_right_hand_sides(dl, dev):
     """Degenerate inputs: a zero right-hand side among others solves to x = 0 in no iterations with
     status OK (BiCGStab in FP64 and in FP32 with FP64 reliable updates, and the truncated CGNR),
