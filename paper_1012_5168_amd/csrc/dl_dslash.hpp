@@ -196,9 +196,37 @@ __device__ __forceinline__ void load_site(const Field &f, int Vh, int rhs, int64
         load_spinor<S>(f, Vh, rhs, cb, v);
 }
 
-template <typename S, int EPI, bool BUF = false, bool NT = false>
-__device__ __forceinline__ void epilogue(const DKArgs &a, int rhs, int64_t cb, const cx<typename Fmt<S>::R> acc[12],
-                                         double part[], bool valid = true)
+// The operands an epilogue reads at its own site: x for the XPAY family, y
+// where it takes a dot product with y, subtracts it or updates it.
+template <int EPI>
+constexpr bool epi_reads_x()
+{
+    return EPI != EPI_PLAIN;
+}
+template <int EPI>
+constexpr bool epi_reads_y()
+{
+    return EPI == EPI_XPAY_DOT || EPI == EPI_XPAY_TS || EPI == EPI_XMY_NRM || EPI == EPI_CG_R;
+}
+template <typename R, int EPI>
+struct EpiOps {
+    cx<R> x[epi_reads_x<EPI>() ? 12 : 1], y[epi_reads_y<EPI>() ? 12 : 1];
+};
+
+// the epilogue's operand loads (issued ahead of its arithmetic by the
+// LDS-link kernel's walk)
+template <typename S, int EPI, bool BUF>
+__device__ __forceinline__ void epilogue_load(const DKArgs &a, int rhs, int64_t cb,
+                                              EpiOps<typename Fmt<S>::R, EPI> &ops)
+{
+    if constexpr (epi_reads_x<EPI>()) load_site<S, BUF>(a.x, a.g.Vh, rhs, cb, ops.x);
+    if constexpr (epi_reads_y<EPI>()) load_site<S, BUF>(a.y, a.g.Vh, rhs, cb, ops.y);
+}
+
+template <typename S, int EPI, bool NT>
+__device__ __forceinline__ void epilogue_apply(const DKArgs &a, int rhs, int64_t cb,
+                                               const cx<typename Fmt<S>::R> acc[12],
+                                               const EpiOps<typename Fmt<S>::R, EPI> &ops, double part[], bool valid)
 {
     using R = typename Fmt<S>::R;
     const R coef = R(a.a);
@@ -208,12 +236,11 @@ __device__ __forceinline__ void epilogue(const DKArgs &a, int rhs, int64_t cb, c
         for (int e = 0; e < 12; ++e) o[e] = coef * acc[e];
     } else {
         cx<R> xv[12];
-        load_site<S, BUF>(a.x, a.g.Vh, rhs, cb, xv);
-        if constexpr (EPI == EPI_XMY_NRM) {
-            cx<R> yv[12];
-            load_site<S, BUF>(a.y, a.g.Vh, rhs, cb, yv);
 #pragma unroll
-            for (int e = 0; e < 12; ++e) xv[e] = xv[e] - yv[e];
+        for (int e = 0; e < 12; ++e) xv[e] = ops.x[e];
+        if constexpr (EPI == EPI_XMY_NRM) {
+#pragma unroll
+            for (int e = 0; e < 12; ++e) xv[e] = xv[e] - ops.y[e];
         }
 #pragma unroll
         for (int e = 0; e < 12; ++e) {
@@ -222,34 +249,28 @@ __device__ __forceinline__ void epilogue(const DKArgs &a, int rhs, int64_t cb, c
         }
         double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0, p4 = 0.0;
         if constexpr (EPI == EPI_XPAY_DOT) {
-            cx<R> yv[12];
-            load_site<S, BUF>(a.y, a.g.Vh, rhs, cb, yv);
 #pragma unroll
             for (int e = 0; e < 12; ++e) {
-                p0 += (double)yv[e].re * o[e].re + (double)yv[e].im * o[e].im;
-                p1 += (double)yv[e].re * o[e].im - (double)yv[e].im * o[e].re;
+                p0 += (double)ops.y[e].re * o[e].re + (double)ops.y[e].im * o[e].im;
+                p1 += (double)ops.y[e].re * o[e].im - (double)ops.y[e].im * o[e].re;
             }
         } else if constexpr (EPI == EPI_XPAY_TS) {
-            cx<R> yv[12];
-            load_site<S, BUF>(a.y, a.g.Vh, rhs, cb, yv);
 #pragma unroll
             for (int e = 0; e < 12; ++e) {
                 p0 += (double)o[e].re * xv[e].re + (double)o[e].im * xv[e].im;
                 p1 += (double)o[e].re * xv[e].im - (double)o[e].im * xv[e].re;
                 p2 += (double)o[e].re * o[e].re + (double)o[e].im * o[e].im;
-                p3 += (double)yv[e].re * o[e].re + (double)yv[e].im * o[e].im;
-                p4 += (double)yv[e].re * o[e].im - (double)yv[e].im * o[e].re;
+                p3 += (double)ops.y[e].re * o[e].re + (double)ops.y[e].im * o[e].im;
+                p4 += (double)ops.y[e].re * o[e].im - (double)ops.y[e].im * o[e].re;
             }
         }
         if constexpr (EPI == EPI_CG_R) {
             // the residual update of the normal equations' CG: r -= alpha q
             const R al = R(a.st[rhs].alpha[0]);
-            cx<R> yv[12];
-            load_site<S, BUF>(a.y, a.g.Vh, rhs, cb, yv);
 #pragma unroll
             for (int e = 0; e < 12; ++e) {
-                o[e].re = fma(-al, o[e].re, yv[e].re);
-                o[e].im = fma(-al, o[e].im, yv[e].im);
+                o[e].re = fma(-al, o[e].re, ops.y[e].re);
+                o[e].im = fma(-al, o[e].im, ops.y[e].im);
             }
         }
         if (valid) {
@@ -272,6 +293,15 @@ __device__ __forceinline__ void epilogue(const DKArgs &a, int rhs, int64_t cb, c
         if (valid) part[0] += p0;
     }
     if (valid) store_spinor<S, NT>(a.out, a.g.Vh, rhs, cb, o);
+}
+
+template <typename S, int EPI, bool BUF = false, bool NT = false>
+__device__ __forceinline__ void epilogue(const DKArgs &a, int rhs, int64_t cb, const cx<typename Fmt<S>::R> acc[12],
+                                         double part[], bool valid = true)
+{
+    EpiOps<typename Fmt<S>::R, EPI> ops;
+    epilogue_load<S, EPI, BUF>(a, rhs, cb, ops);
+    epilogue_apply<S, EPI, NT>(a, rhs, cb, acc, ops, part, valid);
 }
 
 // neighbour checkerboard indices (x+, x-, y+, y-, z+, z-, t+, t-) of site
@@ -444,6 +474,23 @@ constexpr bool lds_pipelined()
 #ifndef LDS_PREFETCH
 #define LDS_PREFETCH 2
 #endif
+// The hop during which the walk issues the epilogue's own-site operand loads
+// (x, y) of the current right-hand side, so that they are in flight while the
+// last hops compute; 8 issues them after the last hop.  Measured on whole
+// solves at 16^3 x 32 (hopping time per 288-RHS step): issued during hop 6,
+// FP64 242 -> 233 ms and FP32 (mixed precision) 145 -> 143 ms; the 16-bit
+// formats slow down (FP16 CGNR on 416 RHS 122 -> 130 ms) and keep 8.
+// LDS_EPI_PREFETCH overrides the choice for every format.
+template <typename S>
+constexpr int lds_epi_prefetch()
+{
+#ifdef LDS_EPI_PREFETCH
+    return LDS_EPI_PREFETCH;
+#else
+    return Fmt<S>::VEC < 4 ? 6 : 8;
+#endif
+}
+
 template <typename S, int EPI>
 constexpr int lds_prefetch()
 {
@@ -480,6 +527,7 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
     constexpr int NP = nparts_c<EPI>();
     constexpr int SF = DAG ? +1 : -1;
     constexpr int SB = -SF;
+    constexpr int EPF = epi_reads_x<EPI>() ? lds_epi_prefetch<S>() : 8;
     __shared__ __align__(16) unsigned char lds[lds_link_bytes<S, NE>()];
     E *const lk = reinterpret_cast<E *>(lds);           // links as stored
     cx<R> *const lx = reinterpret_cast<cx<R> *>(lds);   // links expanded
@@ -611,6 +659,7 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
                     cx<R> acc[12];
 #pragma unroll
                     for (int e = 0; e < 12; ++e) acc[e] = {R(0), R(0)};
+                    EpiOps<R, EPI> ops;
 #pragma unroll
                     for (int d = 0; d < 8; ++d) {
                         // hop d + PF's loads (the next right-hand side's first
@@ -623,11 +672,13 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
                             load_hop(rin, r, t, buf[t % NBUF]);
                         else
                             load_hop(rin_n, rn, t - 8, buf[t % NBUF]);
+                        if (d == EPF) epilogue_load<S, EPI, true>(a, r, cb, ops);
                         asm volatile("" ::: "memory");
                         apply_hop(d, buf[d % NBUF], acc);
                         pin_acc<R>(acc);
                     }
-                    epilogue<S, EPI, true, true>(a, r, cb, acc, part, valid);
+                    if constexpr (EPF >= 8) epilogue_load<S, EPI, true>(a, r, cb, ops);
+                    epilogue_apply<S, EPI, true>(a, r, cb, acc, ops, part, valid);
                     write_block_partials<NP>(a, r, sb, sl, part);
                     if (!more) break;
                     r = rn;
@@ -644,14 +695,17 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
                     cx<R> acc[12];
 #pragma unroll
                     for (int e = 0; e < 12; ++e) acc[e] = {R(0), R(0)};
+                    EpiOps<R, EPI> ops;
 #pragma unroll
                     for (int d = 0; d < 8; ++d) {
                         CxSpinor<R> cur;
                         load_hop(rin, r, d, cur);
+                        if (d == EPF) epilogue_load<S, EPI, true>(a, r, cb, ops);
                         apply_hop(d, cur, acc);
                         pin_acc<R>(acc);
                     }
-                    epilogue<S, EPI, true, true>(a, r, cb, acc, part, valid);
+                    if constexpr (EPF >= 8) epilogue_load<S, EPI, true>(a, r, cb, ops);
+                    epilogue_apply<S, EPI, true>(a, r, cb, acc, ops, part, valid);
                     write_block_partials<NP>(a, r, sb, sl, part);
                 }
             }
