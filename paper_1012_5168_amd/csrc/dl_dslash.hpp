@@ -453,15 +453,22 @@ __device__ __forceinline__ void reserve_waves()
         asm volatile("" ::: "v191");
 }
 
-// Whether the LDS-link kernel double-buffers its neighbour loads.  Measured on
-// 288 right-hand sides at 16^3 x 32: FP64 (one wavefront per SIMD, registers
-// to spare) and BF16 gain 4-8%; FP32 runs at the occupancy it compiles to and
-// the second buffer costs it wavefronts (5% slower), so it walks one hop at a
-// time.
+// Whether the LDS-link kernel prefetches its neighbour loads (pipelined walk)
+// or walks one hop at a time.  Measured on 288 right-hand sides at 16^3 x 32:
+// FP64 (one wavefront per SIMD, registers to spare) and BF16 gained 4-8%.
+// FP32 lost 5% while its links were staged as stored (its occupancy was then
+// set by registers); with expanded links the LDS caps it first, and the
+// pipelined walk takes the plain FP32 launch from 974 to 906 us (the tuner
+// then picks one wavefront per block) and the FP32 hopping time of a
+// mixed-precision step from 146 to 142 ms.  LDS_PIPELINE_F32=0 builds FP32
+// with the serial walk.
+#ifndef LDS_PIPELINE_F32
+#define LDS_PIPELINE_F32 1
+#endif
 template <typename S>
 constexpr bool lds_pipelined()
 {
-    return !std::is_same<S, float>::value;
+    return !std::is_same<S, float>::value || LDS_PIPELINE_F32;
 }
 
 // How many hops ahead the pipelined walk issues its neighbour loads (1 or 2;
