@@ -476,8 +476,12 @@ constexpr bool lds_pipelined()
 // sides on 16^3 x 32: two hops ahead speed the plain FP64 launch up from 1868
 // to 1842 us and the plain BF16 one from 636 to 627 us; FP16 is unchanged,
 // and the FP64 epilogue variants slow down (x + a D in with a dot product
-// 2624 -> 3006 us: 250 registers instead of 220), so only the plain FP64 and
-// BF16 launches take two.  LDS_PREFETCH=1 builds every variant with one.
+// 2624 -> 3006 us: 250 registers instead of 220), so of FP64 and BF16 only
+// the plain launches take two.  FP32, whose occupancy the LDS sets, takes
+// two in every variant (its epilogue variants hold 150-218 registers without
+// spills; FP32 hopping time of a mixed-precision 288-RHS step 142 -> 138 ms).
+// LDS_PREFETCH=1 builds the plain launches with one, LDS_PREFETCH_EPI_F32=1
+// the FP32 epilogue variants.
 #ifndef LDS_PREFETCH
 #define LDS_PREFETCH 2
 #endif
@@ -498,9 +502,13 @@ constexpr int lds_epi_prefetch()
 #endif
 }
 
+#ifndef LDS_PREFETCH_EPI_F32
+#define LDS_PREFETCH_EPI_F32 2
+#endif
 template <typename S, int EPI>
 constexpr int lds_prefetch()
 {
+    if constexpr (EPI != EPI_PLAIN && std::is_same<S, float>::value) return LDS_PREFETCH_EPI_F32;
     return (EPI == EPI_PLAIN && !std::is_same<S, __half>::value) ? LDS_PREFETCH : 1;
 }
 
