@@ -414,7 +414,8 @@ def kernel_name(cfg):
     kind, nr, bs, pg = cfg
     what = "plain half dslash D_oe, FP64, 12-parameter links"
     if kind == 1:
-        occ = "as compiled" if bs == 0 else "at most %d per SIMD" % bs
+        # two 64-site blocks per CU fit the LDS (72 KiB of expanded FP64 links each)
+        occ = ("%d per CU, set by the LDS" % (2 * nr)) if bs == 0 else "at most %d per SIMD" % bs
         return ("dslash_lds_kernel<double,6,false,0,%d,%d> (%s; links of 64-site blocks in LDS, %d wavefronts "
                 "(%s), regions of %d blocks)" % (nr, bs, what, nr, occ, pg))
     return "dslash_kernel<double,6,false,0,%d> (%s; %d sites per workgroup%s)" % (
