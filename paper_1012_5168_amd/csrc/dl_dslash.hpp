@@ -485,6 +485,16 @@ constexpr bool lds_pipelined()
 #ifndef LDS_PREFETCH
 #define LDS_PREFETCH 2
 #endif
+#ifndef LDS_PREFETCH_EPI_F32
+#define LDS_PREFETCH_EPI_F32 2
+#endif
+template <typename S, int EPI>
+constexpr int lds_prefetch()
+{
+    if constexpr (EPI != EPI_PLAIN && std::is_same<S, float>::value) return LDS_PREFETCH_EPI_F32;
+    return (EPI == EPI_PLAIN && !std::is_same<S, __half>::value) ? LDS_PREFETCH : 1;
+}
+
 // The hop during which the walk issues the epilogue's own-site operand loads
 // (x, y) of the current right-hand side, so that they are in flight while the
 // last hops compute; 8 issues them after the last hop.  Measured on whole
@@ -500,16 +510,6 @@ constexpr int lds_epi_prefetch()
 #else
     return Fmt<S>::VEC < 4 ? 6 : 8;
 #endif
-}
-
-#ifndef LDS_PREFETCH_EPI_F32
-#define LDS_PREFETCH_EPI_F32 2
-#endif
-template <typename S, int EPI>
-constexpr int lds_prefetch()
-{
-    if constexpr (EPI != EPI_PLAIN && std::is_same<S, float>::value) return LDS_PREFETCH_EPI_F32;
-    return (EPI == EPI_PLAIN && !std::is_same<S, __half>::value) ? LDS_PREFETCH : 1;
 }
 
 // a neighbour spinor converted to the arithmetic precision
