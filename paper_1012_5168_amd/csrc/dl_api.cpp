@@ -1402,23 +1402,27 @@ struct Stopwatch {
 
 // Algorithmic bytes of one right-hand side's field operands in a solve: every
 // operand of every kernel the solve runs for it, moved once (the links, which
-// the whole batch shares, are not counted).  Per iteration: BiCGStab moves 25
-// half fields in the iteration precision (the p update 4, two plain hops 2
-// each, the hop with the (rhat, v) dot 4, the s update 3, the hop with the
-// (t, s) and |t|^2 sums 3, the x and r update with its sums 7); the truncated
-// CGNR 16 (four hops 2 + 3 + 2 + 4, the last of them forming q and updating r
-// in its epilogue, and the fused x and p update 5).  A reliable update moves 8 FP64 half fields (two for the fold, 2 + 4
-// for the FP64 residual hops, one for the copy back) and 3 in the iteration
-// precision; the set-up 12 FP64 and 7 iteration-precision half fields
-// (source norms, prepared source, zeroed vectors, the first dot) and the
-// reconstruction of the odd sites 3 FP64 half fields.
+// the whole batch shares, are not counted).  Per iteration: BiCGStab moves 24
+// half fields in the iteration precision (the hops 2 + 4 + 2 + 4, the s
+// update 4, the fused x / r / p update 8); the truncated CGNR 16 (four hops
+// 2 + 3 + 2 + 4, the last of them forming q and updating r in its epilogue,
+// and the fused x and p update 5).  A reliable update moves 9 FP64 half
+// fields (2 for the fold, 2 + 4 for the FP64 residual hops, 1 for the
+// replacement of r) and 7 in the iteration precision (the fold 2, the
+// replacement of r and p with (rhat, r) 5); without iterations below FP64
+// there is no fold.  The set-up and the reconstruction of the odd sites move
+// 10 FP64 half fields (source norms 2, prepared source 3, zeroed x 1, the copy
+// into r 1, reconstruction 3) and 8 in the iteration precision (r, rhat = r,
+// p = r, the first dot, zeroed low-precision x).
 double solve_bytes(const SolveWork &w, const KState &k, bool cgnr)
 {
     const double vh = (double)w.r.Vh;
     const double fb = vh * (12.0 * elem_bytes(w.prec) + (w.prec == P16 ? 4.0 : 0.0));
     if (cgnr) return k.iters * 16.0 * fb + 8.0 * fb;
     const double f8 = vh * 12.0 * 16.0;
-    return k.iters * 25.0 * fb + k.updates * (8.0 * f8 + 3.0 * fb) + 15.0 * f8 + 7.0 * fb;
+    const bool mixed = w.prec != P64;
+    const double upd = mixed ? 9.0 * f8 + 7.0 * fb : 7.0 * f8 + 5.0 * fb;
+    return k.iters * 24.0 * fb + k.updates * upd + 10.0 * f8 + 8.0 * fb;
 }
 
 // Per right-hand side statistics of the solve just finished; `seconds` is the
