@@ -196,6 +196,23 @@ def copy_rate(torch):
     return 2 * 8 * n / (ms * 1e-3) / 1e9
 
 
+def stream_rates(dl, torch):
+    """The library's own streaming probe (dl_stream_probe: 16-byte non-temporal loads and stores,
+    tiles of contiguous words, eight loads in flight per thread): a 2 GiB copy (2 GiB read + 2 GiB
+    written) and a 4 GiB read, event-timed; GB/s of bytes moved."""
+    a = torch.ones(1 << 28, dtype=torch.float64, device="cuda")  # 2 GiB
+    b = torch.empty_like(a)
+    dl.stream_probe(a, b, 0, reps=1)
+    copy_s = dl.stream_probe(a, b, 0, reps=5)
+    big = torch.ones(1 << 29, dtype=torch.float64, device="cuda")  # 4 GiB
+    dl.stream_probe(big, b, 1, reps=1)
+    read_s = dl.stream_probe(big, b, 1, reps=5)
+    out = {"copy_gbs": round(2 * a.numel() * 8 / copy_s / 1e9, 1), "read_gbs": round(big.numel() * 8 / read_s / 1e9, 1)}
+    del a, b, big
+    torch.cuda.empty_cache()
+    return out
+
+
 def hop_rate(dl, torch, G, nrhs, prec, reps=3):
     """Plain half-dslash launches of D applied to nrhs right-hand sides at one storage precision:
     (launches, algorithmic GB/s, mean event-timed launch in us, launch configuration).  The first
@@ -582,6 +599,11 @@ def main():
         cg = copy_rate(torch)
         out["copy_reference_gbs"] = round(cg, 1)
         out["roofline"]["frac_of_copy"] = round(plain_gbs / cg, 4)
+        # the library's own streaming kernels: the rate its access pattern gets from the memory system
+        st = stream_rates(dl, torch)
+        out["stream_reference_gbs"] = st
+        out["roofline"]["frac_of_stream_copy"] = round(plain_gbs / st["copy_gbs"], 4)
+        out["roofline"]["frac_of_stream_read"] = round(plain_gbs / st["read_gbs"], 4)
         out["dslash_by_precision"] = dslash_sweep(dl, torch, G, cg)
         out["differentiation"] = differentiation_measurement(dl, torch)
     if not args.no_cpu_baseline:

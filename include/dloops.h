@@ -486,6 +486,23 @@ int64_t dl_profile_read(int32_t kind, double *ms, double *bytes);
  */
 int dl_profile_config(int32_t kind, int32_t *cfg);
 
+/*
+ * Measurement helper, not part of the method: the rate the memory system
+ * gives the library's own access pattern, to compare kernels with.  Mode 0
+ * (copy) reads `bytes` of src and writes them to dst; mode 1 (read) reads
+ * `bytes` of src and writes nothing but, should the running XOR of a thread's
+ * words hit one fixed value, one 16-byte word per workgroup to dst (dst must
+ * hold 128 KiB).  Both use 16-byte non-temporal loads (and stores): up to
+ * 8192 workgroups of 256 threads walk tiles of 2048 contiguous words, eight
+ * loads in flight per thread, each wavefront instruction covering 1 KiB, as
+ * the field kernels access a component plane.  The pass runs `reps` times on
+ * `stream` between HIP events and *seconds receives the mean time of one
+ * pass.  src and dst are device pointers, 16-byte aligned and not
+ * overlapping, bytes a non-zero multiple of 16; DL_EINVAL otherwise.
+ */
+int dl_stream_probe(const void *src, void *dst, uint64_t bytes, int32_t mode, int32_t reps, void *stream,
+                    double *seconds);
+
 #ifdef __cplusplus
 }
 #endif

@@ -135,6 +135,8 @@ _SIGNATURES = {
     "dl_cache_bytes": (ctypes.c_uint64, []),
     "dl_profile_enable": (ctypes.c_int, [ctypes.c_int32]),
     "dl_profile_config": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "dl_stream_probe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     "dl_profile_read": (ctypes.c_int64, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double)]),
 }
@@ -411,6 +413,20 @@ def dl_profile_config(kind: int):
     cfg = (ctypes.c_int32 * 4)()
     _check(load().dl_profile_config(int(kind), cfg))
     return tuple(int(v) for v in cfg)
+
+
+def stream_probe(src, dst, mode: int, reps: int = 5, stream=None) -> float:
+    """Mean seconds of one pass of the library's streaming probe (dl_stream_probe): mode 0 copies
+    src's bytes into dst, mode 1 reads them.  src and dst are device tensors; dst holds at least
+    src's bytes (copy) or 128 KiB (read)."""
+    nbytes = src.numel() * src.element_size()
+    need = nbytes if mode == 0 else 131072
+    if dst.numel() * dst.element_size() < need:
+        raise DLError(DL_EINVAL, "stream_probe: dst too small")
+    sec = ctypes.c_double()
+    _check(load().dl_stream_probe(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                  ctypes.c_uint64(nbytes), int(mode), int(reps), _stream(stream), ctypes.byref(sec)))
+    return sec.value
 
 
 def dl_profile_read(kind: int):

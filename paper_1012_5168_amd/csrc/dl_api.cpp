@@ -2265,6 +2265,55 @@ extern "C" int dl_profile_config(int32_t kind, int32_t *cfg)
     return DL_OK;
 }
 
+namespace {
+// two HIP events, destroyed on every exit
+struct EventPair {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    EventPair()
+    {
+        DL_HIP(hipEventCreate(&e0));
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            throw Error{DL_EHIP, "hipEventCreate failed"};
+        }
+    }
+    ~EventPair()
+    {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    EventPair(const EventPair &) = delete;
+    EventPair &operator=(const EventPair &) = delete;
+};
+}  // namespace
+
+extern "C" int dl_stream_probe(const void *src, void *dst, uint64_t bytes, int32_t mode, int32_t reps, void *stream,
+                               double *seconds)
+{
+    return guarded([&]() {
+        DL_REQUIRE(src && dst && seconds, "dl_stream_probe: null pointer");
+        DL_REQUIRE(mode == 0 || mode == 1, "dl_stream_probe: mode must be 0 (copy) or 1 (read)");
+        DL_REQUIRE(reps >= 1, "dl_stream_probe: reps must be at least 1");
+        DL_REQUIRE(bytes > 0 && bytes % 16 == 0, "dl_stream_probe: bytes must be a non-zero multiple of 16");
+        DL_REQUIRE((uintptr_t)src % 16 == 0 && (uintptr_t)dst % 16 == 0,
+                   "dl_stream_probe: src and dst must be 16-byte aligned");
+        const uintptr_t a0 = (uintptr_t)src, b0 = (uintptr_t)dst;
+        const uint64_t span = mode == 0 ? bytes : 131072;
+        DL_REQUIRE(a0 + bytes <= b0 || b0 + span <= a0, "dl_stream_probe: src and dst overlap");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        EventPair ev;
+        DL_HIP(hipEventRecord(ev.e0, s));
+        for (int r = 0; r < reps; ++r) stream_launch(mode, src, dst, (int64_t)(bytes / 16), s);
+        DL_HIP(hipGetLastError());
+        DL_HIP(hipEventRecord(ev.e1, s));
+        DL_HIP(hipEventSynchronize(ev.e1));
+        float ms = 0.0f;
+        DL_HIP(hipEventElapsedTime(&ms, ev.e0, ev.e1));
+        *seconds = (double)ms * 1e-3 / reps;
+        return DL_OK;
+    });
+}
+
 extern "C" int64_t dl_profile_read(int32_t kind, double *ms, double *bytes)
 {
     if (kind < 0 || kind >= PROF_NKIND) return DL_EINVAL;

@@ -263,6 +263,8 @@ enum VOp { V_BICG_S = 0, V_BICG_XRP, V_CG_XR, V_CG_P, V_ZERO, V_NORM2, V_DOT };
 void vec_launch(int op, int prec, const std::vector<VSeg> &segs, hipStream_t s);
 void copy_launch(int prec_dst, int prec_src, const std::vector<VSeg> &segs, hipStream_t s);  // f0 = f1
 void fold_launch(int prec, const std::vector<VSeg> &segs, hipStream_t s);   // f0 (FP64) += f1; f1 = 0
+// measurement only: copy (mode 0) or read (mode 1) nwords 16-byte words with non-temporal accesses
+void stream_launch(int mode, const void *src, void *dst, int64_t nwords, hipStream_t s);
 // reliable update of the residual: f0 (r, precision prec) = f1 (FP64 residual), and the search
 // direction f2 (p, precision prec) += f1 - old f0, so that p = r + beta (p - omega v) holds for the
 // replaced r

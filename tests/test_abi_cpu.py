@@ -81,6 +81,28 @@ def test_null_handles_rejected(dl):
     assert lib.dl_loops_smeared(None, 0.1, None, 0.5, 2, p, None, 1, None, None, None) == dl.DL_EINVAL
 
 
+def test_stream_probe_arguments_rejected_before_device_work(dl):
+    """dl_stream_probe validates its arguments before any device work: null pointers, a mode other
+    than copy / read, reps < 1, a size that is zero or not a multiple of 16, misaligned or
+    overlapping buffers all return DL_EINVAL (fake, never dereferenced addresses)."""
+    import ctypes
+
+    lib = dl.load()
+    sec = ctypes.c_double()
+    ok_a, ok_b = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 30)
+    assert lib.dl_stream_probe(None, ok_b, 1024, 0, 1, None, ctypes.byref(sec)) == dl.DL_EINVAL
+    assert lib.dl_stream_probe(ok_a, ok_b, 1024, 0, 1, None, None) == dl.DL_EINVAL
+    assert lib.dl_stream_probe(ok_a, ok_b, 1024, 2, 1, None, ctypes.byref(sec)) == dl.DL_EINVAL
+    assert lib.dl_stream_probe(ok_a, ok_b, 1024, 0, 0, None, ctypes.byref(sec)) == dl.DL_EINVAL
+    assert lib.dl_stream_probe(ok_a, ok_b, 0, 0, 1, None, ctypes.byref(sec)) == dl.DL_EINVAL
+    assert lib.dl_stream_probe(ok_a, ok_b, 1000, 0, 1, None, ctypes.byref(sec)) == dl.DL_EINVAL
+    assert lib.dl_stream_probe(ctypes.c_void_p((1 << 20) + 8), ok_b, 1024, 0, 1, None, ctypes.byref(sec)) == \
+        dl.DL_EINVAL
+    assert lib.dl_stream_probe(ok_a, ctypes.c_void_p((1 << 20) + 512), 1024, 0, 1, None, ctypes.byref(sec)) == \
+        dl.DL_EINVAL
+    assert "dl_stream_probe" in dl.dl_last_error()
+
+
 def test_correlator_arguments_rejected_before_device_work(dl):
     """Too few noises, an empty time extent, a non-positive volume or a null pointer return
     DL_EINVAL without touching the GPU."""

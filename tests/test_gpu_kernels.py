@@ -205,3 +205,24 @@ def test_many_rhs_chunks_both_kernels(dl, dev, kernel):
         assert status == dl.DL_OK and res <= 1e-12, (kernel, r, st[r])
         rr = np.linalg.norm(b[r] - oracle.apply_m(U, sol[r], dims, kappa)) / np.linalg.norm(b[r])
         assert rr <= 1.5e-12, (kernel, r, rr)
+
+
+@pytest.mark.gpu
+def test_stream_probe_copies_and_reads(dl, dev):
+    """The streaming probe behind the bench's measured ceilings: mode 0 copies every byte of a
+    ragged buffer (not a multiple of the 2048-word tiles: the tail loop runs too), mode 1 reads
+    without writing, and both report a positive time."""
+    n = (1 << 22) + 6  # complex128 entries: 16-byte words, ragged
+    a = torch.randn(n, dtype=torch.complex128, device=dev)
+    b = torch.zeros_like(a)
+    sec = dl.stream_probe(a, b, 0, reps=2)
+    torch.cuda.synchronize()
+    assert sec > 0
+    assert torch.equal(a, b)
+    c = torch.zeros(1 << 14, dtype=torch.float64, device=dev)  # 128 KiB
+    sec = dl.stream_probe(a, c, 1, reps=2)
+    torch.cuda.synchronize()
+    assert sec > 0
+    assert torch.count_nonzero(c).item() == 0
+    with pytest.raises(dl.DLError):
+        dl.stream_probe(a, c, 0)  # dst too small for a copy
