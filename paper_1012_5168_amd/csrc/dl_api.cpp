@@ -234,7 +234,7 @@ void HalfField::alloc(int prec_, int64_t nrhs_, int64_t Vh_)
     prec = prec_;
     nrhs = nrhs_;
     Vh = Vh_;
-    data.alloc((size_t)nrhs * 12 * Vh * elem_bytes(prec));
+    data.alloc((size_t)nrhs * rhs_stride_bytes(Vh, elem_bytes(prec)));
     if (prec == P16)
         nrm.alloc((size_t)nrhs * Vh * sizeof(float));
     else
@@ -244,7 +244,7 @@ void HalfField::alloc(int prec_, int64_t nrhs_, int64_t Vh_)
 Field HalfField::view_rhs(int64_t r) const
 {
     Field f;
-    f.d = static_cast<char *>(data.p) + (size_t)r * 12 * Vh * elem_bytes(prec);
+    f.d = static_cast<char *>(data.p) + (size_t)r * rhs_stride_bytes(Vh, elem_bytes(prec));
     f.nrm = nrm.p ? nrm.as<float>() + r * Vh : nullptr;
     return f;
 }
@@ -757,7 +757,7 @@ void *scratch_on_current_device()
 // bytes of one packed field of n right-hand sides, rounded up to 256
 size_t field_span(int prec, int n, int64_t Vh)
 {
-    const size_t d = (size_t)n * 12 * Vh * elem_bytes(prec);
+    const size_t d = (size_t)n * rhs_stride_bytes(Vh, elem_bytes(prec));
     const size_t m = prec == P16 ? (size_t)n * Vh * sizeof(float) : 0;
     auto up = [](size_t b) { return (b + 255) / 256 * 256; };
     return up(d) + up(m);
@@ -765,7 +765,7 @@ size_t field_span(int prec, int n, int64_t Vh)
 
 Field carve(char *&p, int prec, int n, int64_t Vh)
 {
-    const size_t d = ((size_t)n * 12 * Vh * elem_bytes(prec) + 255) / 256 * 256;
+    const size_t d = ((size_t)n * rhs_stride_bytes(Vh, elem_bytes(prec)) + 255) / 256 * 256;
     Field f{p, nullptr};
     p += d;
     if (prec == P16) {
@@ -868,12 +868,12 @@ struct SolveWork {
     }
     static size_t bytes_bicg(int prec, int64_t Vh)
     {
-        size_t f64 = 12 * 16 * Vh, fl = 12 * elem_bytes(prec) * Vh + (prec == P16 ? 4 * Vh : 0);
+        size_t f64 = rhs_stride_bytes(Vh, 16), fl = rhs_stride_bytes(Vh, elem_bytes(prec)) + (prec == P16 ? 4 * Vh : 0);
         return 7 * f64 + (prec == P64 ? 6 : 7) * fl + 8 * 8 * ((Vh + 63) / 64) + 256;
     }
     static size_t bytes_cgnr(int prec, int64_t Vh)
     {
-        size_t fl = 12 * elem_bytes(prec) * Vh + (prec == P16 ? 4 * Vh : 0);
+        size_t fl = rhs_stride_bytes(Vh, elem_bytes(prec)) + (prec == P16 ? 4 * Vh : 0);
         return 10 * fl + 8 * 8 * ((Vh + 63) / 64) + 256;
     }
 };
@@ -1658,8 +1658,8 @@ int loops_run(dl_gauge G, double kappa, const dl_sources *src, const dl_solve_pa
     const bool cg = prm.solver == DL_CGNR;
     size_t per = (cg ? SolveWork::bytes_cgnr(prm.prec, Vh) : SolveWork::bytes_bicg(prm.prec, Vh)) +
                  (size_t)T * 32 * 8 + 16;
-    if (mode == MODE_GRAD) per += 2 * (size_t)Vh * 12 * 16;  // the stored forward solution
-    if (smear_iters > 0) per += 4 * (size_t)Vh * 12 * 16;    // smeared source and its ping-pong partner
+    if (mode == MODE_GRAD) per += 2 * (size_t)rhs_stride_bytes(Vh, 16);  // the stored forward solution
+    if (smear_iters > 0) per += 4 * (size_t)rhs_stride_bytes(Vh, 16);    // smeared source and its ping-pong partner
     const int64_t total = (int64_t)src->n_noise * ncls;
     const int nsolve = mode == MODE_LOOPS ? 1 : (mode == MODE_GRAD && dout_host) ? 3 : 2;
     const int B = batch_size(per, total, ncls);

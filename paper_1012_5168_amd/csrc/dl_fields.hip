@@ -545,8 +545,8 @@ void k_smear(const void *links, int recon, Field ine, Field ino, Field oute, Fie
     const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(nrhs, 0x7fffffff / nblk));
     for (int r0 = 0; r0 < nrhs; r0 += chunk) {
         const int n = std::min(chunk, nrhs - r0);
-        auto sub = [&](Field f) {  // FP64 fields: [rhs][12][Vh] complex, no scales
-            f.d = static_cast<char *>(f.d) + (size_t)r0 * 12 * g.Vh * 16;
+        auto sub = [&](Field f) {  // FP64 fields: [rhs][12][Vh] complex (and the gap), no scales
+            f.d = static_cast<char *>(f.d) + (size_t)r0 * rhs_stride_bytes(g.Vh, 16);
             return f;
         };
         const dim3 grid((unsigned)(nblk * n));

@@ -228,7 +228,7 @@ TuneChoice tune_lookup(const std::vector<DslashCall> &c, hipStream_t s)
     if (in_place(c)) {
         try {
             for (DslashCall &d : t) {
-                const size_t data = (size_t)d.nrhs * 12 * (size_t)d.g.Vh * elem_bytes(d.prec);
+                const size_t data = (size_t)d.nrhs * rhs_stride_bytes(d.g.Vh, elem_bytes(d.prec));
                 const size_t nrm = d.prec == P16 ? (size_t)d.nrhs * (size_t)d.g.Vh * sizeof(float) : 0;
                 scratch.emplace_back(data + nrm);
                 d.out.d = scratch.back().p;
