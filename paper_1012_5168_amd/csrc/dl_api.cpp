@@ -1674,7 +1674,7 @@ int loops_run(dl_gauge G, double kappa, const dl_sources *src, const dl_solve_pa
         dA.alloc(A.size() * sizeof(double));
         DL_HIP(hipMemcpyAsync(dA.p, A.data(), dA.bytes, hipMemcpyHostToDevice, c.s));
         dgrad.alloc((size_t)4 * V * 9 * 16);
-        k_zero(P64, Field{dgrad.p, nullptr}, (int64_t)4 * V * 9 / 12, 1, nullptr, c.s);  // [4][V][9] complex
+        zero_launch(dgrad.p, (int64_t)4 * V * 9, c.s);  // [4][V][9] complex
     }
     int worst = DL_OK;
     Stopwatch sw;

@@ -731,6 +731,21 @@ __global__ __launch_bounds__(256) void stream_kernel(const U4v *src, U4v *dst, i
             dst[blockIdx.x] = acc;
 }
 
+// nwords 16-byte words of zeros from p on (flat buffers that are no packed
+// field, such as the link gradient)
+__global__ __launch_bounds__(256) void fill_zero_kernel(U4v *p, int64_t n)
+{
+    const U4v z = {0u, 0u, 0u, 0u};
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = z;
+}
+
+void zero_launch(void *p, int64_t nwords, hipStream_t s)
+{
+    if (nwords <= 0) return;
+    const int grid = (int)std::min<int64_t>((nwords + 255) / 256, PERSIST);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(grid), dim3(256), 0, s, static_cast<U4v *>(p), nwords);
+}
+
 // Read mode writes at most one word per workgroup: dst needs STREAM_GRID x 16
 // bytes (128 KiB).
 void stream_launch(int mode, const void *src, void *dst, int64_t nwords, hipStream_t s)

@@ -278,16 +278,27 @@ __host__ __device__ constexpr int comp_of(int j, int q)
 }
 
 // Bytes from one right-hand side of a packed half field to the next: its 12
-// component planes and a gap of RHS_GAP bytes.  Where Vh * 16 is a multiple of
-// a large power of two (1 MiB for FP64 at 16^3 x 32) the planes of every
-// right-hand side would start at multiples of it and fall into the same L2
-// sets, so that the few right-hand sides a hopping launch has in flight evict
-// each other's neighbour spinors; the gap moves each right-hand side's planes
-// to other sets.  Measured on the plain FP64 hop of 288 right-hand sides at
-// 16^3 x 32: 1.71x -> 1.66x its input bytes fetched, 1877 -> 1797 us (a gap
-// of 16.5 KiB: 1843 us).
+// component planes and a gap of RHS_GAP bytes; and 16-byte vectors from one
+// plane to the next: Vh and a gap of PLANE_GAP (1 KiB).  Where Vh * 16 is a
+// multiple of a large power of two (1 MiB for FP64 at 16^3 x 32) the planes of
+// every right-hand side would all start at multiples of it.  Across right-hand
+// sides that puts the few a hopping launch has in flight into the same L2
+// sets, where they evict each other's neighbour spinors: with the RHS gap the
+// plain FP64 hop of 288 right-hand sides at 16^3 x 32 fetched 1.66x instead of
+// 1.71x its input bytes and took 1797 instead of 1877 us (a gap of 16.5 KiB:
+// 1843 us).  The plane gap does not change the bytes fetched but took the same
+// launch from 1786-1829 to 1737-1751 us (192 vectors: 1764-1786 us); the
+// concurrent streams of one right-hand side's planes then no longer start at
+// one offset modulo 1 MiB.
 constexpr int64_t RHS_GAP = 1024;
-__host__ __device__ constexpr int64_t rhs_stride_bytes(int64_t Vh, int64_t elem) { return 12 * Vh * elem + RHS_GAP; }
+#ifndef PLANE_GAP
+#define PLANE_GAP 64
+#endif
+__host__ __device__ constexpr int64_t plane_stride(int64_t Vh) { return Vh + PLANE_GAP; }
+__host__ __device__ constexpr int64_t rhs_stride_bytes(int64_t Vh, int64_t elem)
+{
+    return 12 * elem * plane_stride(Vh) + RHS_GAP;
+}
 
 template <typename S>
 __device__ __forceinline__ const char *spinor_base(const Field &f, int64_t Vh, int rhs)
@@ -309,10 +320,10 @@ __device__ __forceinline__ void load_spinor(const Field &f, int64_t Vh, int rhs,
     for (int j = 0; j < 12 / V; ++j) {
         uint4 q;
         if constexpr (NT) {
-            const U4 raw = __builtin_nontemporal_load(reinterpret_cast<const U4 *>(p) + ((int64_t)j * Vh + cb));
+            const U4 raw = __builtin_nontemporal_load(reinterpret_cast<const U4 *>(p) + ((int64_t)j * plane_stride(Vh) + cb));
             __builtin_memcpy(&q, &raw, 16);
         } else {
-            q = p[(int64_t)j * Vh + cb];
+            q = p[(int64_t)j * plane_stride(Vh) + cb];
         }
         cx<R> t[V];
         F::unpack(q, t);
@@ -338,11 +349,11 @@ __device__ __forceinline__ void load_half(const Field &f, int64_t Vh, int rhs, i
     const char *base = spinor_base<S>(f, Vh, rhs);
     const uint4 *p = reinterpret_cast<const uint4 *>(base);
     if constexpr (V == 4) {
-        F::unpack(p[(int64_t)H * Vh + cb], v);
-        F::unpack2(reinterpret_cast<const uint2 *>(base)[(2 * Vh + cb) * 2 + H], v + 4);
+        F::unpack(p[(int64_t)H * plane_stride(Vh) + cb], v);
+        F::unpack2(reinterpret_cast<const uint2 *>(base)[(2 * plane_stride(Vh) + cb) * 2 + H], v + 4);
     } else {
 #pragma unroll
-        for (int j = 0; j < 6 / V; ++j) F::unpack(p[(int64_t)(H * 6 / V + j) * Vh + cb], v + j * V);
+        for (int j = 0; j < 6 / V; ++j) F::unpack(p[(int64_t)(H * 6 / V + j) * plane_stride(Vh) + cb], v + j * V);
     }
     if constexpr (F::scaled) {
         const R s = f.nrm[(int64_t)rhs * Vh + cb];
@@ -352,15 +363,16 @@ __device__ __forceinline__ void load_half(const Field &f, int64_t Vh, int rhs, i
 }
 
 // One right-hand side's half-spinor field as a buffer resource (its 12/VEC
-// vectors of 16 bytes per site, vector j of site cb at byte (j Vh + cb) 16).
-// A neighbour's loads then share one per-site byte offset in a VGPR and take
-// the vector offset j Vh 16 from a scalar register: no 64-bit address
-// arithmetic per load.  Requires 12 Vh sizeof(E) < 2^31 (checked by the
-// launcher).  Reads past the resource return zero instead of faulting.
+// vectors of 16 bytes per site, vector j of site cb at byte (j Vp + cb) 16
+// with Vp = plane_stride(Vh)).  A neighbour's loads then share one per-site
+// byte offset in a VGPR and take the vector offset j Vp 16 from a scalar
+// register: no 64-bit address arithmetic per load.  Requires
+// 12 Vp sizeof(E) < 2^31 (checked by the launcher).  Reads past the resource
+// return zero instead of faulting.
 template <typename S>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t spinor_rsrc(const Field &f, int Vh, int rhs)
 {
-    const int bytes = 12 * Vh * (int)sizeof(typename Fmt<S>::E);
+    const int bytes = 12 * (int)plane_stride(Vh) * (int)sizeof(typename Fmt<S>::E);
     char *base = static_cast<char *>(f.d) + (int64_t)rhs * rhs_stride_bytes(Vh, sizeof(typename Fmt<S>::E));
     // word 3: 32-bit data format, the value raw buffer loads use on this family
     return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, bytes, 0x00020000);
@@ -386,7 +398,7 @@ __device__ __forceinline__ void load_spinor_rsrc(__amdgpu_buffer_rsrc_t rs, cons
     const int voff = cb * 16;
 #pragma unroll
     for (int j = 0; j < 12 / V; ++j) {
-        const auto raw = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, j * Vh * 16, AUX);
+        const auto raw = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, j * (int)plane_stride(Vh) * 16, AUX);
         uint4 q;
         __builtin_memcpy(&q, &raw, 16);
         cx<R> t[V];
@@ -411,18 +423,19 @@ __device__ __forceinline__ void load_half_rsrc(__amdgpu_buffer_rsrc_t rs, const 
     constexpr int V = F::VEC;
     const int voff = cb * 16;
     if constexpr (V == 4) {
-        const auto raw = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, H * Vh * 16, AUX);
+        const auto raw = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, H * (int)plane_stride(Vh) * 16, AUX);
         uint4 q;
         __builtin_memcpy(&q, &raw, 16);
         F::unpack(q, v);
-        const auto raw2 = __builtin_amdgcn_raw_buffer_load_b64(rs, voff + 8 * H, 2 * Vh * 16, AUX);
+        const auto raw2 = __builtin_amdgcn_raw_buffer_load_b64(rs, voff + 8 * H, 2 * (int)plane_stride(Vh) * 16, AUX);
         uint2 q2;
         __builtin_memcpy(&q2, &raw2, 8);
         F::unpack2(q2, v + 4);
     } else {
 #pragma unroll
         for (int j = 0; j < 6 / V; ++j) {
-            const auto raw = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, (H * 6 / V + j) * Vh * 16, AUX);
+            const auto raw =
+                __builtin_amdgcn_raw_buffer_load_b128(rs, voff, (H * 6 / V + j) * (int)plane_stride(Vh) * 16, AUX);
             uint4 q;
             __builtin_memcpy(&q, &raw, 16);
             F::unpack(q, v + j * V);
@@ -451,7 +464,7 @@ __device__ __forceinline__ void store_spinor(const Field &f, int64_t Vh, int rhs
 #pragma unroll
         for (int k = 0; k < V; ++k) t[k] = w[comp_of<V>(j, k)];
         const uint4 q = F::pack(t);
-        const int64_t k = (int64_t)j * Vh + cb;
+        const int64_t k = (int64_t)j * plane_stride(Vh) + cb;
         if constexpr (NT) {
             U4 raw;
             __builtin_memcpy(&raw, &q, 16);

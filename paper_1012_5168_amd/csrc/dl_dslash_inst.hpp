@@ -76,7 +76,7 @@ template <typename S>
 bool dslash_lds_fits(const DslashCall *c, int nseg)
 {
     for (int k = 0; k < nseg; ++k)
-        if (12LL * c[k].g.Vh * (long long)sizeof(typename Fmt<S>::E) >= (1LL << 31)) return false;
+        if (12LL * plane_stride(c[k].g.Vh) * (long long)sizeof(typename Fmt<S>::E) >= (1LL << 31)) return false;
     return true;
 }
 

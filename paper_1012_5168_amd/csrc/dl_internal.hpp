@@ -265,6 +265,7 @@ void copy_launch(int prec_dst, int prec_src, const std::vector<VSeg> &segs, hipS
 void fold_launch(int prec, const std::vector<VSeg> &segs, hipStream_t s);   // f0 (FP64) += f1; f1 = 0
 // measurement only: copy (mode 0) or read (mode 1) nwords 16-byte words with non-temporal accesses
 void stream_launch(int mode, const void *src, void *dst, int64_t nwords, hipStream_t s);
+void zero_launch(void *p, int64_t nwords, hipStream_t s);  // nwords 16-byte words
 // reliable update of the residual: f0 (r, precision prec) = f1 (FP64 residual), and the search
 // direction f2 (p, precision prec) += f1 - old f0, so that p = r + beta (p - omega v) holds for the
 // replaced r
