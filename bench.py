@@ -431,10 +431,11 @@ def kernel_name(cfg):
     kind, nr, bs, pg = cfg
     what = "plain half dslash D_oe, FP64, 12-parameter links"
     if kind == 1:
-        # two 64-site blocks per CU fit the LDS (72 KiB of expanded FP64 links each)
-        occ = ("%d per CU, set by the LDS" % (2 * nr)) if bs == 0 else "at most %d per SIMD" % bs
-        return ("dslash_lds_kernel<double,6,false,0,%d,%d> (%s; links of 64-site blocks in LDS, %d wavefronts "
-                "(%s), regions of %d blocks)" % (nr, bs, what, nr, occ, pg))
+        # four 64-site blocks per CU fit the LDS (36 KiB of spatial FP64 links as stored each; the
+        # temporal links sit in registers)
+        occ = ("%d per CU, set by the LDS" % (4 * nr)) if bs == 0 else "at most %d per SIMD" % bs
+        return ("dslash_lds_kernel<double,6,false,0,%d,%d> (%s; spatial links of 64-site blocks in LDS, temporal "
+                "links in registers, %d wavefronts per block (%s), regions of %d blocks)" % (nr, bs, what, nr, occ, pg))
     return "dslash_kernel<double,6,false,0,%d> (%s; %d sites per workgroup%s)" % (
         nr, what, bs, ", persistent grid of %d" % pg if pg else "")
 

@@ -424,17 +424,34 @@ constexpr int LDS_SITES = 64;
 // Whether the LDS holds the links expanded (9 complex numbers per link in the
 // arithmetic precision) or as stored (NE entries in the storage format,
 // converted and completed per use).
+// LDS_TLINK_REGS (FP64): the LDS holds only the six spatial links, as stored,
+// and every wavefront keeps its site's two temporal links expanded in
+// registers, so that four blocks fit per CU (36 KiB each with 12-parameter
+// links) and an XCD's whole share of a 16^3 x 32 lattice (four timeslices,
+// 128 blocks) is resident at once: a region then reads a quarter more input
+// than its own (the two neighbouring timeslices' spin pairs) instead of a
+// half.  Measured on the all-live plain launch of 288 right-hand sides with
+// one wavefront per block and regions of 128 blocks: 1.48x instead of 1.65x
+// the input and links fetched, 1688-1714 against 1736-1761 us with the
+// expanded links in LDS (two blocks per CU, regions of 64).
+template <typename S>
+constexpr bool lds_tregs()
+{
+    return LDS_TLINK_REGS && std::is_same<S, double>::value;
+}
+
 template <typename S, int NE>
 constexpr bool lds_expanded()
 {
-    return !LDS_COMPACT_LINKS;
+    return !LDS_COMPACT_LINKS && !lds_tregs<S>();
 }
 
 template <typename S, int NE>
 constexpr int lds_link_bytes()
 {
-    return lds_expanded<S, NE>() ? 8 * 9 * LDS_SITES * (int)sizeof(cx<typename Fmt<S>::R>)
-                                 : 8 * NE * LDS_SITES * (int)sizeof(typename Fmt<S>::E);
+    return lds_tregs<S>()           ? 6 * NE * LDS_SITES * (int)sizeof(typename Fmt<S>::E)
+           : lds_expanded<S, NE>() ? 8 * 9 * LDS_SITES * (int)sizeof(cx<typename Fmt<S>::R>)
+                                   : 8 * NE * LDS_SITES * (int)sizeof(typename Fmt<S>::E);
 }
 
 // Reserve registers so that at most OCC wavefronts share a SIMD (0: the
@@ -547,8 +564,16 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
     E *const lk = reinterpret_cast<E *>(lds);           // links as stored
     cx<R> *const lx = reinterpret_cast<cx<R> *>(lds);   // links expanded
     reserve_waves<OCC>();
+    cx<R> ut[2][9];  // the temporal links in registers (lds_tregs)
     // the link of hop d at this lane's site, all three rows
     auto load_u = [&](int d, int sl_, cx<R> u[9]) {
+        if constexpr (lds_tregs<S>()) {
+            if (d >= 6) {
+#pragma unroll
+                for (int e = 0; e < 9; ++e) u[e] = ut[d - 6][e];
+                return;
+            }
+        }
         if constexpr (lds_expanded<S, NE>()) {
 #pragma unroll
             for (int e = 0; e < 9; ++e) u[e] = lx[(d * 9 + e) * LDS_SITES + sl_];
@@ -592,6 +617,7 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
         neighbours(g, cb, s, nb);
         __syncthreads();  // the previous item's links are no longer read
         for (int d = w; d < 8; d += LANES) {
+            if (lds_tregs<S>() && d >= 6) continue;
             const int mu = d >> 1, bwd = d & 1;
             const int lcb = bwd ? nb[d] : cb;
             const E *src = static_cast<const E *>(a.links) + ((int64_t)(mu * 2 + (bwd ? q : p)) * NE) * g.Vh + lcb;
@@ -604,6 +630,10 @@ __global__ __launch_bounds__(LDS_SITES *LANES) void dslash_lds_kernel(Segs<DKArg
 #pragma unroll
                 for (int e = 0; e < NE; ++e) lk[(d * NE + e) * LDS_SITES + sl] = src[(int64_t)e * g.Vh];
             }
+        }
+        if constexpr (lds_tregs<S>()) {
+            load_link<S, NE>(a.links, g.Vh, 3, p, cb, ut[0]);
+            load_link<S, NE>(a.links, g.Vh, 3, q, nb[7], ut[1]);
         }
         __syncthreads();
 

@@ -218,9 +218,16 @@ constexpr int LDS_WORKGROUP_BYTES = 163840;
 #ifndef LDS_COMPACT_LINKS
 #define LDS_COMPACT_LINKS 0
 #endif
+// FP64: only the six spatial links in LDS, as stored (36 KiB per block with
+// 12-parameter links, so four blocks per CU), the two temporal links of a
+// wavefront's sites in its registers (1)
+#ifndef LDS_TLINK_REGS
+#define LDS_TLINK_REGS 1
+#endif
 // bytes of links one 64-site block of the LDS-link kernel keeps in LDS
 inline int lds_link_block_bytes(int prec, int recon)
 {
+    if (LDS_TLINK_REGS && prec == P64) return 6 * (recon == 12 ? 6 : 9) * 64 * 16;
     return LDS_COMPACT_LINKS ? 8 * (recon == 12 ? 6 : 9) * 64 * (int)elem_bytes(prec)
                              : 8 * 9 * 64 * (prec == P64 ? 16 : 8);
 }

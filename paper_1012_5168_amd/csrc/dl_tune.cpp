@@ -20,10 +20,11 @@
 // with its output redirected to a scratch field of the same size); a
 // candidate replaces the default only if it is 3%
 // faster, and the result is kept in memory and in a text cache file
-// (DL_TUNE_CACHE, default ~/.cache/dloops/tune_gfx950_v4.txt).
+// (DL_TUNE_CACHE, default ~/.cache/dloops/tune_gfx950_v5.txt).
 // DL_TUNE=0 disables tuning and uses the default: the LDS-link kernel with 2
-// wavefronts, one wavefront per SIMD (for FP64 the LDS alone enforces it) and
-// regions of 64 blocks where its links fit in LDS, else the item kernel with
+// wavefronts, one wavefront per SIMD and regions of 64 blocks where its links
+// fit in LDS (FP64 with 12-parameter links: 1 wavefront per block, four
+// blocks per CU, regions of 128 blocks), else the item kernel with
 // 1 right-hand side per thread and 256 sites per workgroup; DL_TUNE=item and
 // DL_TUNE=lds pin those two choices (the latter where the LDS-link kernel
 // applies); DL_TUNE=cfg:kind:nr:bs:grid pins one configuration the launcher
@@ -74,7 +75,7 @@ std::string cache_path()
 {
     if (const char *p = std::getenv("DL_TUNE_CACHE")) return p;
     const char *home = std::getenv("HOME");
-    return std::string(home ? home : "/tmp") + "/.cache/dloops/tune_gfx950_v4.txt";
+    return std::string(home ? home : "/tmp") + "/.cache/dloops/tune_gfx950_v5.txt";
 }
 
 // DL_TUNE: unset or anything else = tune; "0" = default; "item" / "lds" =
@@ -102,8 +103,7 @@ int lds_waves_per_simd(int prec, int recon, int lanes)
 }
 
 // The candidate set; a cached choice outside it is ignored.  An occupancy cap
-// that the LDS already enforces (the FP64 links of a block take 72 KiB, so
-// two wavefronts per block are one per SIMD) is no separate candidate.
+// that the LDS already enforces is no separate candidate.
 std::vector<TuneChoice> candidates(int prec, int recon)
 {
     std::vector<TuneChoice> v;
@@ -136,6 +136,9 @@ bool launchable(const TuneChoice &t, int prec, int recon)
 TuneChoice default_choice(int prec, int recon)
 {
     if (!dslash_lds_ok(prec, recon)) return TuneChoice{0, 1, 256, 0};
+    // FP64 with its temporal links in registers: one wavefront per block,
+    // four blocks per CU, regions of 128 blocks
+    if (LDS_TLINK_REGS && prec == P64 && recon == 12) return TuneChoice{1, 1, 0, 128};
     return TuneChoice{1, 2, lds_waves_per_simd(prec, recon, 2) > 1 ? 1 : 0, 64};
 }
 
