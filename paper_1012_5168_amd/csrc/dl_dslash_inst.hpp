@@ -2,6 +2,8 @@
 // precision (included once per precision so the variants compile in parallel).
 #pragma once
 
+#include <algorithm>
+
 #include "dl_dslash.hpp"
 
 namespace dl {
@@ -117,6 +119,9 @@ void launch_dslash_t(const DslashCall *c, int nseg, int kind, int nr, int bs, in
     int grid, rb = 0;
     if (kind == 1) {
         rb = persistent > 0 ? persistent : 64;
+        // a region is at most an XCD's share, so that every XCD gets work on
+        // lattices of fewer than 8 rb site blocks
+        rb = std::max(1, std::min(rb, (total + 7) / 8));
         const int nreg = (total + rb - 1) / rb;
         grid = 8 * ((nreg + 7) / 8) * rb;
     } else {
