@@ -423,7 +423,7 @@ def synth_workload(name):
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, KiB -> bytes, mean over the 174
 # dispatches of the warm-up, timed and unprofiled steps), keyed by the launch
 # configuration they were taken with.  Another configuration reports null.
-PROFILED_TRAFFIC = {(1, 2, 0, 64): 7.98e9}
+PROFILED_TRAFFIC = {(1, 1, 0, 128): 7.42e9}
 
 
 def kernel_name(cfg):
