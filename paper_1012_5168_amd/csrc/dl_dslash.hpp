@@ -410,7 +410,8 @@ __global__ __launch_bounds__(256) void dslash_kernel(Segs<DKArgs> B)
 // A workgroup owns 64 consecutive checkerboard sites (one wavefront wide) and
 // keeps their 8 link matrices in LDS, expanded to all three rows in the
 // arithmetic precision (converted and rebuilt once per block, not once per
-// right-hand side and hop); its LANES wavefronts then walk the
+// right-hand side and hop; FP64 keeps the six spatial ones as stored and the
+// two temporal ones in registers, see lds_tregs); its LANES wavefronts then walk the
 // right-hand sides (wavefront w takes w, w + LANES, ...), so every link is
 // read from memory once per launch instead of once per right-hand side.
 // Site blocks are grouped into regions of rb consecutive blocks; region i
@@ -458,9 +459,11 @@ constexpr int lds_link_bytes()
 // occupancy the kernel compiles to).  The register file of a SIMD lane holds
 // 512 registers (VGPRs and AGPRs together): claiming v255 and a31 leaves room
 // for one wavefront, claiming v191 for two.  The FP64 LDS-link kernel runs
-// best at one wavefront per SIMD (measured at 288 right-hand sides: 9 GB
-// fetched per launch instead of 13-14 GB, a third faster); capping the blocks
-// per CU through LDS instead, at the same wavefronts per CU, does not do it.
+// best at one wavefront per SIMD (measured at 288 right-hand sides with all
+// links in LDS: 9 GB fetched per launch instead of 13-14 GB, a third faster);
+// capping the blocks per CU through LDS instead, at the same wavefronts per
+// CU, does not do it.  With its temporal links in registers it compiles to
+// one wavefront per SIMD by itself.
 template <int OCC>
 __device__ __forceinline__ void reserve_waves()
 {

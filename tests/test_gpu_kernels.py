@@ -1,5 +1,7 @@
 """Both hopping kernels (the item kernel and the LDS-link kernel, the latter
-at several wavefront counts, occupancy limits and region sizes) against the
+at several wavefront counts, occupancy limits and region sizes, regions
+larger than a lattice's share of an XCD included; FP64 with its temporal
+links in registers) against the
 FP64 oracle, each pinned through DL_TUNE so that none depends on which one the
 autotuner prefers on the day.
 
